@@ -1,0 +1,210 @@
+/*
+ * qpmi.h -- C ABI of libqpmi.so, a batched, differentiable dense QP solver
+ * for AMD MI355X (gfx950), after the OptNet layer of Amos & Kolter (2017).
+ *
+ * Every problem is the quadratic program of Section 3, eq. qp2:
+ *
+ *     minimize_z   1/2 z^T Q z + q^T z
+ *     subject to   A z = b,   G z <= h
+ *
+ * with z in R^nz, Q in R^{nz x nz} (only its symmetric part (Q + Q^T)/2 is
+ * used; it must be positive definite on the null space of A, and the method
+ * as built needs Q + G^T D G positive definite, which holds for Q > 0),
+ * A in R^{neq x nz} of full row rank, G in R^{nineq x nz}.
+ *
+ * Naming.  The paper calls the equality count m and the inequality count p
+ * (A in R^{m x n}, G in R^{p x n}); this header uses nz (variables),
+ * nineq (rows of G, h, lambda, s) and neq (rows of A, b, nu) instead.
+ *
+ * Memory.  Every pointer argument named as "device" is a HIP device pointer
+ * on the current device; arrays are row-major and batch-major.  The caller
+ * owns every buffer (inputs, outputs, state and workspace); the library never
+ * allocates device memory and keeps no per-call global state.  Calls are
+ * asynchronous on the given stream (a hipStream_t passed as void*, NULL =
+ * the default stream) and are thread-safe for distinct buffers.
+ *
+ * Errors.  Call-level errors are negative return codes detected on the host
+ * before any launch, with outputs untouched.  Per-problem outcomes are written
+ * asynchronously into status[] (QP_STATUS_*) and iters[].
+ */
+#ifndef QPMI_H
+#define QPMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- types -------------------------------------------------------------- */
+
+typedef enum { QP_F32 = 0, QP_F64 = 1 } qp_dtype;
+
+/* Call-level return codes. */
+enum {
+    QP_OK = 0,
+    QP_EARG = -1,    /* bad dims, batch, stride or a NULL required pointer    */
+    QP_EWS = -2,     /* workspace smaller than qp_workspace_query() requires  */
+    QP_EDTYPE = -3,  /* unknown dtype                                         */
+    QP_EHIP = -4,    /* a HIP launch failed; qp_last_hip_error() has the code */
+    QP_ENODEV = -5,  /* no usable gfx950 device / code object                 */
+    QP_ETOOBIG = -6  /* a problem exceeds the library's size limits           */
+};
+
+/* Per-problem outcomes written to status[]. */
+enum {
+    QP_STATUS_OPTIMAL = 0,   /* stopping test met (see qp_opts.tol)                     */
+    QP_STATUS_MAX_ITER = 1,  /* max_iter Newton steps taken; last iterate returned      */
+    QP_STATUS_BREAKDOWN = 2, /* non-positive or non-finite pivot in the factorization of
+                                the returned iterate; the iterate is returned, the
+                                stored factor (and so any backward) is undefined         */
+    QP_STATUS_NONFINITE = 3  /* non-finite input or iterate                              */
+};
+
+typedef struct {
+    int32_t nz;    /* variables, >= 1             */
+    int32_t nineq; /* inequality rows, >= 0       */
+    int32_t neq;   /* equality rows, 0 <= neq < nz */
+} qp_dims;
+
+/* Solver options (qp_default_opts fills them per dtype). */
+typedef struct {
+    int32_t max_iter;     /* Newton steps after the initial point (default 20)          */
+    int32_t refine_steps; /* iterative-refinement steps in the backward solve
+                             (default 1 for F64, 3 for F32)                              */
+    double tol;           /* stop when max(mu, |r_x|inf, |r_s|inf, |r_y|inf) <= tol,
+                             mu = s^T lambda / nineq (default 1e-8 F64, 1e-3 F32)        */
+    int32_t variant;      /* kernel variant: 0 = pick automatically, else a QP_VARIANT_* */
+    uint32_t flags;       /* reserved, must be 0                                         */
+} qp_opts;
+
+enum {
+    QP_VARIANT_AUTO = 0,
+    QP_VARIANT_GENERIC = 1, /* one workgroup per problem, factor in global memory        */
+    QP_VARIANT_LDS = 2,     /* one workgroup per problem, factor resident in LDS          */
+    QP_VARIANT_TILED = 3    /* LDS-resident, MFMA-tiled formation/factorization (gfx950)   */
+};
+
+/* Problem data of a uniform batch: device pointers plus per-problem strides in
+ * elements between consecutive problems (0 = the array is shared by the whole
+ * batch).  Within a problem: Q [nz*nz], q [nz], A [neq*nz], b [neq],
+ * G [nineq*nz], h [nineq], all contiguous row-major.  A/b (G/h) may be NULL
+ * when neq (nineq) is 0. */
+typedef struct {
+    const void *Q, *q, *A, *b, *G, *h;
+    int64_t sQ, sq, sA, sb, sG, sh;
+} qp_data;
+
+/* ---- queries -------------------------------------------------------------- */
+
+/* Fill *opts with the defaults for dtype.  Returns QP_OK or QP_EDTYPE. */
+int32_t qp_default_opts(qp_dtype dtype, qp_opts *opts);
+
+/* Bytes of the opaque per-problem factor `state` written by the forward and
+ * read by the backward (the factor of the symmetrised KKT matrix of
+ * Section 3.1.1 at the returned iterate).  The state of a batch is
+ * batch * (*state_bytes), problem i at offset i * (*state_bytes). */
+int32_t qp_state_bytes(qp_dtype dtype, qp_dims dims, size_t *state_bytes);
+
+/* Bytes of device workspace a forward / backward call over `batch` problems
+ * of `dims` needs (may be 0).  The workspace is scratch: contents are not
+ * preserved across calls and it may be reused once the call has completed
+ * on its stream. */
+int32_t qp_workspace_query(qp_dtype dtype, int32_t batch, qp_dims dims, const qp_opts *opts,
+                           size_t *fwd_ws_bytes, size_t *bwd_ws_bytes);
+
+/* ---- forward ---------------------------------------------------------------- */
+
+/* Solve `batch` QPs by the primal-dual interior point method of Section 3.1
+ * (affine direction, eq. cvxgen:affine; centering-plus-corrector direction,
+ * eq. cvxgen:cc; symmetrised KKT system reduced to (Q + G^T D G) with a Schur
+ * complement on A, factored by Cholesky once per iterate).
+ * Outputs (device, written for every problem):
+ *   z [batch*nz], lam [batch*nineq], nu [batch*neq], s [batch*nineq] (slacks),
+ *   state [batch*state_bytes] (opaque factor for qp_backward_batched),
+ *   status [batch] (QP_STATUS_*), iters [batch] (Newton steps taken).
+ * lam/s may be NULL iff nineq == 0, nu iff neq == 0.
+ * ws: device workspace of at least fwd_ws_bytes (NULL when that is 0). */
+int32_t qp_forward_batched(qp_dtype dtype, int32_t batch, qp_dims dims, const qp_data *data,
+                           const qp_opts *opts, void *z, void *lam, void *nu, void *s, void *state,
+                           int32_t *status, int32_t *iters, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ---- backward ----------------------------------------------------------------- */
+
+/* Gradients of a loss l through the QP solution (Section 3.1.1): solve
+ * eq. grads-system with the stored factor (no new factorization) plus
+ * opts->refine_steps steps of iterative refinement on the unreduced
+ * symmetrised KKT residual, then form eq. grads:
+ *   dQ = 1/2 (d_z z^T + z d_z^T), dq = d_z, dA = d_nu z^T + nu d_z^T,
+ *   db = -d_nu, dG = D(lam) d_lam z^T + lam d_z^T, dh = -D(lam) d_lam.
+ * Inputs (device): data (the same problem data as the forward), z, lam, nu, s,
+ * state (as written by the forward), dl_dz [batch*nz].
+ * Outputs (device, nullable = not requested), per problem and contiguous:
+ *   dQ [batch*nz*nz], dq [batch*nz], dA [batch*neq*nz], db [batch*neq],
+ *   dG [batch*nineq*nz], dh [batch*nineq].
+ * Gradients of batch-shared inputs (stride 0) are still written per problem;
+ * summing them over the batch is the caller's choice. */
+int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims dims, const qp_data *data,
+                            const qp_opts *opts, const void *z, const void *lam, const void *nu,
+                            const void *s, const void *state, const void *dl_dz, void *dQ,
+                            void *dq, void *dA, void *db, void *dG, void *dh, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* ---- uneven batches ------------------------------------------------------------ */
+
+/* One problem of an uneven batch.  All offsets are in elements of the dtype
+ * (state: in bytes) into the base pointers of the call; arrays of one problem
+ * are contiguous row-major as in qp_data. */
+typedef struct {
+    int32_t nz, nineq, neq, variant; /* variant: as qp_opts.variant, 0 = auto     */
+    int64_t Q, q, A, b, G, h;        /* input offsets (element)                   */
+    int64_t z, lam, nu;              /* output offsets: z/dq, lam/s/dh, nu/db     */
+    int64_t state;                   /* byte offset into state (qp_state_bytes)   */
+} qp_problem_desc;
+
+/* Solve `count` problems of different sizes in one persistent launch.
+ * desc_dev: device array of `count` descriptors; desc_host: the same array in
+ * host memory (used to size the launch; never retained).  `order_dev`
+ * (device, `count` int32, may be NULL = identity) gives the order in which
+ * workgroups pick problems (largest first balances the launch).
+ * base_in: element base pointer of the packed inputs (Q..h of every problem);
+ * z, lam, nu, s: element base pointers of the packed outputs (s uses the lam
+ * offsets); state: byte base pointer; status/iters: [count] device.
+ * ws must hold fwd bytes from qp_varlen_workspace_query. */
+int32_t qp_varlen_workspace_query(qp_dtype dtype, int32_t count, const qp_problem_desc *desc_host,
+                                  const qp_opts *opts, size_t *fwd_ws_bytes, size_t *bwd_ws_bytes,
+                                  size_t *state_bytes_total);
+
+int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *desc_dev,
+                          const qp_problem_desc *desc_host, const int32_t *order_dev,
+                          const void *base_in, const qp_opts *opts, void *z, void *lam, void *nu,
+                          void *s, void *state, int32_t *status, int32_t *iters, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Backward of an uneven batch.  Gradient outputs use the input offsets of the
+ * descriptors (dQ at desc.Q, dq at desc.q, ... in packed buffers shaped like the
+ * inputs); `grad_base` may be NULL for problems that need no gradient only if
+ * `need_dev` marks them: need_dev (device, `count` int32, NULL = all) selects
+ * the problems whose gradients are computed; others are skipped. dl_dz uses
+ * the z offsets. */
+int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *desc_dev,
+                           const qp_problem_desc *desc_host, const int32_t *need_dev,
+                           const void *base_in, const qp_opts *opts, const void *z,
+                           const void *lam, const void *nu, const void *s, const void *state,
+                           const void *dl_dz, void *grad_base, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ---- diagnostics ---------------------------------------------------------------- */
+
+/* The hipError_t of the last QP_EHIP return on this thread (0 if none). */
+int32_t qp_last_hip_error(void);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t qp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPMI_H */

@@ -1,0 +1,246 @@
+// Backward kernels (Section 3.1.1, eq. grads-system and eq. grads).
+//
+// Kernel 1 (one workgroup per problem): solve the symmetrised KKT system at
+// the solution with the factor stored by the forward,
+//     K_sym [d_z; d_s; d~_lam; d_nu] = [-dl/dz; 0; 0; 0],
+// where d~_lam = D(lambda) d_lam is the scaled multiplier adjoint, plus
+// refine_steps steps of iterative refinement on the residual of the unreduced
+// K_sym (matrix-vector products with Qs, G, A, D only; no new factorization).
+// The adjoint vectors go to a workspace.
+//
+// Kernel 2 (many workgroups per problem, write-bound): the gradients
+//     dQ = 1/2 (d_z z^T + z d_z^T),  dq = d_z,  dA = d_nu z^T + nu d_z^T,
+//     db = -d_nu,  dG = d~_lam z^T + lambda d_z^T,  dh = -d~_lam.
+#include "qp_core.hpp"
+
+namespace qpmi {
+
+template <typename T>
+struct BProb {
+    int n, m, p;
+    const T *Q, *A, *G;
+    const T *z, *lam, *nu, *s;
+    const char *state;
+    const T *g;
+    T *adj;
+    bool need;
+    // gradient outputs (nullable)
+    T *dQ, *dq, *dA, *db, *dG, *dh;
+};
+
+template <typename T>
+__device__ __forceinline__ BProb<T> bwd_problem(const BwdLaunch &L, int j) {
+    BProb<T> P;
+    P.adj = (T *)L.adj + (size_t)j * L.adj_stride;
+    if (L.desc == nullptr) {
+        P.n = L.nz; P.m = L.nineq; P.p = L.neq;
+        P.Q = (const T *)L.Q + (size_t)j * L.sQ;
+        P.A = (const T *)L.A + (size_t)j * L.sA;
+        P.G = (const T *)L.G + (size_t)j * L.sG;
+        P.z = (const T *)L.z + (size_t)j * P.n;
+        P.lam = (const T *)L.lam + (size_t)j * P.m;
+        P.s = (const T *)L.s + (size_t)j * P.m;
+        P.nu = (const T *)L.nu + (size_t)j * P.p;
+        P.g = (const T *)L.dl_dz + (size_t)j * P.n;
+        P.state = L.state + (size_t)j * L.state_stride;
+        P.need = true;
+        const size_t n = P.n, m = P.m, p = P.p;
+        P.dQ = L.dQ ? (T *)L.dQ + j * n * n : nullptr;
+        P.dq = L.dq ? (T *)L.dq + j * n : nullptr;
+        P.dA = L.dA ? (T *)L.dA + j * p * n : nullptr;
+        P.db = L.db ? (T *)L.db + j * p : nullptr;
+        P.dG = L.dG ? (T *)L.dG + j * m * n : nullptr;
+        P.dh = L.dh ? (T *)L.dh + j * m : nullptr;
+    } else {
+        const qp_problem_desc d = L.desc[j];
+        const T *base = (const T *)L.base_in;
+        P.n = d.nz; P.m = d.nineq; P.p = d.neq;
+        P.Q = base + d.Q; P.A = base + d.A; P.G = base + d.G;
+        P.z = (const T *)L.z + d.z; P.lam = (const T *)L.lam + d.lam;
+        P.s = (const T *)L.s + d.lam; P.nu = (const T *)L.nu + d.nu;
+        P.g = (const T *)L.dl_dz + d.z;
+        P.state = L.state + d.state;
+        P.need = L.need ? (L.need[j] != 0) : true;
+        T *gb = (T *)L.grad_base;
+        P.dQ = gb + d.Q; P.dq = gb + d.q; P.dA = gb + d.A;
+        P.db = gb + d.b; P.dG = gb + d.G; P.dh = gb + d.h;
+    }
+    return P;
+}
+
+struct BwdLayout {
+    int z, g, dz, f, y, tn, tn2, r1, ez;              // n
+    int lam, s, D, dl, ds, r2, r3, tm, el, es, tm2;   // m
+    int nu, dn, r4, tp, tp2, en;                      // p
+    int red, end;
+    __host__ __device__ BwdLayout(int n, int m, int p) {
+        const int N = pad4(n), M = pad4(m), Pp = pad4(p);
+        int o = 0;
+        z = o; o += N; g = o; o += N; dz = o; o += N; f = o; o += N; y = o; o += N;
+        tn = o; o += N; tn2 = o; o += N; r1 = o; o += N; ez = o; o += N;
+        lam = o; o += M; s = o; o += M; D = o; o += M; dl = o; o += M; ds = o; o += M;
+        r2 = o; o += M; r3 = o; o += M; tm = o; o += M; el = o; o += M; es = o; o += M;
+        tm2 = o; o += M;
+        nu = o; o += Pp; dn = o; o += Pp; r4 = o; o += Pp; tp = o; o += Pp; tp2 = o; o += Pp;
+        en = o; o += Pp;
+        red = o; o += 64;
+        end = o;
+    }
+};
+
+size_t bwd_vec_lds_bytes(int esz, int n, int m, int p) { return (size_t)BwdLayout(n, m, p).end * esz; }
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    const int tid = threadIdx.x;
+    for (int j = blockIdx.x; j < L.count; j += gridDim.x) {
+        const BProb<T> P = bwd_problem<T>(L, j);
+        if (!P.need) continue;
+        const int n = P.n, m = P.m, p = P.p;
+        const BwdLayout Lo(n, m, p);
+        const StateLayout SL = state_layout(sizeof(T), n, m, p);
+        const T *U = (const T *)(P.state + SL.off_U);
+        const T *Dst = (const T *)(P.state + SL.off_D);
+        const T *Wt = (const T *)(P.state + SL.off_Wt);
+        const T *US = (const T *)(P.state + SL.off_US);
+        const T *__restrict__ Q = P.Q;
+        const T *__restrict__ G = P.G;
+        const T *__restrict__ A = P.A;
+        T *z = sm + Lo.z, *g = sm + Lo.g, *dz = sm + Lo.dz, *f = sm + Lo.f, *y = sm + Lo.y,
+          *tn = sm + Lo.tn, *tn2 = sm + Lo.tn2, *r1 = sm + Lo.r1, *ez = sm + Lo.ez;
+        T *lam = sm + Lo.lam, *s = sm + Lo.s, *D = sm + Lo.D, *dl = sm + Lo.dl, *ds = sm + Lo.ds,
+          *r2 = sm + Lo.r2, *r3 = sm + Lo.r3, *tm = sm + Lo.tm, *el = sm + Lo.el, *es = sm + Lo.es,
+          *tm2 = sm + Lo.tm2;
+        T *nu = sm + Lo.nu, *dn = sm + Lo.dn, *r4 = sm + Lo.r4, *tp = sm + Lo.tp,
+          *tp2 = sm + Lo.tp2, *en = sm + Lo.en;
+
+        for (int i = tid; i < n; i += NT) { z[i] = P.z[i]; g[i] = P.g[i]; f[i] = -P.g[i]; }
+        for (int k = tid; k < m; k += NT) { lam[k] = P.lam[k]; s[k] = P.s[k]; D[k] = Dst[k]; }
+        for (int k = tid; k < p; k += NT) { nu[k] = P.nu[k]; r4[k] = T(0); }
+        __syncthreads();
+        kkt_solve<T, NT>(U, n, Wt, US, n, p, f, r4, y, tp, tp2, dz, dn);
+        mv_rows<T, NT>(G, n, m, n, dz, tm);
+        __syncthreads();
+        for (int k = tid; k < m; k += NT) { ds[k] = -tm[k]; dl[k] = D[k] * tm[k]; }
+        __syncthreads();
+
+        for (int r = 0; r < L.refine_steps; ++r) {
+            // residual of K_sym [dz; ds; dl; dn] = [-g; 0; 0; 0]
+            mv_rows<T, NT>(Q, n, n, n, dz, tn);
+            mv_cols<T, NT>(Q, n, n, n, dz, tn2);
+            mv_cols<T, NT>(G, n, m, n, dl, r1);
+            mv_rows<T, NT>(G, n, m, n, dz, tm);
+            if (p > 0) {
+                mv_cols<T, NT>(A, n, p, n, dn, y);
+                mv_rows<T, NT>(A, n, p, n, dz, tp);
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += NT) {
+                T acc = T(0.5) * (tn[i] + tn2[i]) + r1[i];
+                if (p > 0) acc += y[i];
+                r1[i] = -g[i] - acc;
+            }
+            for (int k = tid; k < m; k += NT) {
+                const T a2 = -(D[k] * ds[k] + dl[k]);
+                const T a3 = -(tm[k] + ds[k]);
+                r2[k] = a2;
+                r3[k] = a3;
+                tm2[k] = a2 - D[k] * a3;
+            }
+            for (int k = tid; k < p; k += NT) r4[k] = -tp[k];
+            __syncthreads();
+            // correction: f = r1 - G^T (r2 - D r3)
+            mv_cols<T, NT>(G, n, m, n, tm2, f);
+            __syncthreads();
+            for (int i = tid; i < n; i += NT) f[i] = r1[i] - f[i];
+            __syncthreads();
+            kkt_solve<T, NT>(U, n, Wt, US, n, p, f, r4, y, tp, tp2, ez, en);
+            mv_rows<T, NT>(G, n, m, n, ez, tm);
+            __syncthreads();
+            for (int k = tid; k < m; k += NT) {
+                const T e_s = r3[k] - tm[k];
+                const T e_l = r2[k] - D[k] * e_s;
+                ds[k] += e_s;
+                dl[k] += e_l;
+            }
+            for (int i = tid; i < n; i += NT) dz[i] += ez[i];
+            for (int k = tid; k < p; k += NT) dn[k] += en[k];
+            __syncthreads();
+        }
+        for (int i = tid; i < n; i += NT) P.adj[i] = dz[i];
+        for (int k = tid; k < m; k += NT) P.adj[n + k] = dl[k];
+        for (int k = tid; k < p; k += NT) P.adj[n + m + k] = dn[k];
+        __syncthreads();
+    }
+}
+
+// Gradient assembly: blockIdx.x = problem, blockIdx.y = group of kRowsPerBlock
+// rows of the concatenation [dQ (n rows); dG (m rows); dA (p rows); vectors].
+constexpr int kRowsPerBlock = 8;
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void qp_grad_assemble_kernel(BwdLaunch L) {
+    constexpr int NW = NT / 64;
+    const int j = blockIdx.x;
+    const BProb<T> P = bwd_problem<T>(L, j);
+    if (!P.need) return;
+    const int n = P.n, m = P.m, p = P.p;
+    const int R = n + m + p + 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const T *dz = P.adj, *dl = P.adj + n, *dn = P.adj + n + m;
+    const T *z = P.z;
+    for (int rr = w; rr < kRowsPerBlock; rr += NW) {
+        const int r = blockIdx.y * kRowsPerBlock + rr;
+        if (r >= R) break;
+        if (r < n) {
+            if (!P.dQ) continue;
+            const T dzi = dz[r], zi = z[r];
+            T *row = P.dQ + (size_t)r * n;
+            for (int c = lane; c < n; c += 64) row[c] = T(0.5) * (dzi * z[c] + zi * dz[c]);
+        } else if (r < n + m) {
+            if (!P.dG) continue;
+            const int k = r - n;
+            const T a = dl[k], lk = P.lam[k];
+            T *row = P.dG + (size_t)k * n;
+            for (int c = lane; c < n; c += 64) row[c] = a * z[c] + lk * dz[c];
+        } else if (r < n + m + p) {
+            if (!P.dA) continue;
+            const int k = r - n - m;
+            const T a = dn[k], nk = P.nu[k];
+            T *row = P.dA + (size_t)k * n;
+            for (int c = lane; c < n; c += 64) row[c] = a * z[c] + nk * dz[c];
+        } else {
+            if (P.dq) for (int c = lane; c < n; c += 64) P.dq[c] = dz[c];
+            if (P.dh) for (int c = lane; c < m; c += 64) P.dh[c] = -dl[c];
+            if (P.db) for (int c = lane; c < p; c += 64) P.db[c] = -dn[c];
+        }
+    }
+}
+
+constexpr int kBwdThreads = 256;
+
+template <typename T>
+static hipError_t launch_bwd_t(const BwdLaunch &L, hipStream_t st, int max_rows) {
+    if (L.count <= 0) return hipSuccess;
+    auto k1 = qp_backward_solve_kernel<T, kBwdThreads>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        (void)hipFuncSetAttribute((const void *)k1, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(k1, dim3(L.count), dim3(kBwdThreads), L.lds_bytes, st, L);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int gx = (max_rows + kRowsPerBlock - 1) / kRowsPerBlock;
+    hipLaunchKernelGGL((qp_grad_assemble_kernel<T, kBwdThreads>), dim3(L.count, gx), dim3(kBwdThreads),
+                       0, st, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(qp_dtype dt, const BwdLaunch &L, hipStream_t st) {
+    return dt == QP_F64 ? launch_bwd_t<double>(L, st, L.max_rows) : launch_bwd_t<float>(L, st, L.max_rows);
+}
+
+}  // namespace qpmi

@@ -1,0 +1,245 @@
+// Device building blocks shared by the forward and backward kernels.
+//
+// Execution model: one workgroup of NT threads (NT/64 wavefronts of 64 lanes)
+// owns one QP at a time.  Every routine below is called by all threads of the
+// workgroup in uniform control flow and ends with a workgroup barrier when its
+// results are read by other threads.
+//
+// The reduced KKT system.  The symmetrised Newton system of Section 3.1
+// (second block row of K scaled by D(1/s)) has unknowns (dz, ds, dlam, dnu)
+// and the matrix
+//     [ Qs  0  G^T  A^T ]
+//     [ 0   D  I    0   ]      D = D(lambda / s)
+//     [ G   I  0    0   ]
+//     [ A   0  0    0   ]
+// Eliminating ds and dlam leaves [H A^T; A 0] with H = Qs + G^T D G, which
+// is factored as H = L L^T; the Schur complement S = A H^{-1} A^T = Wt Wt^T,
+// Wt = (L^{-1} A^T)^T, is factored as LS LS^T.  The kernels keep the inverse
+// factors U = L^{-T} and US = LS^{-T} (upper triangular), so that every
+// solve is a pair of triangular matrix-vector products.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "qp_internal.h"
+
+namespace qpmi {
+
+__host__ __device__ constexpr int pad4(int x) { return (x + 3) & ~3; }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Workgroup reductions of up to three values at once (sum, max, min), the
+// result returned to every thread.  Fixed order => deterministic.
+template <typename T, int NT>
+__device__ __forceinline__ void block_reduce3(T &vsum, T &vmax, T &vmin, T *red) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T a = wave_sum(vsum), b = wave_max(vmax), c = wave_min(vmin);
+    if (lane == 0) { red[w] = a; red[NW + w] = b; red[2 * NW + w] = c; }
+    __syncthreads();
+    a = red[0]; b = red[NW]; c = red[2 * NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) { a += red[i]; b = fmax(b, red[NW + i]); c = fmin(c, red[2 * NW + i]); }
+    __syncthreads();
+    vsum = a; vmax = b; vmin = c;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ T block_sum(T v, T *red) {
+    T mx = 0, mn = 0;
+    block_reduce3<T, NT>(v, mx, mn, red);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T pinf() { return __builtin_huge_val(); }
+template <>
+__device__ __forceinline__ float pinf<float>() { return __builtin_huge_valf(); }
+
+// ---------------------------------------------------------------------------
+// Dense matrix-vector products.  M is row-major with leading dimension ld.
+
+// y[c] = sum_{r<rows} M[r][c] x[r]   (one thread per column, coalesced rows)
+template <typename T, int NT>
+__device__ __forceinline__ void mv_cols(const T *__restrict__ M, int ld, int rows, int cols,
+                                        const T *x, T *y) {
+    for (int c = threadIdx.x; c < cols; c += NT) {
+        T acc = 0;
+        for (int r = 0; r < rows; ++r) acc += M[(size_t)r * ld + c] * x[r];
+        y[c] = acc;
+    }
+}
+
+// y[r] = sum_{c<cols} M[r][c] x[c]   (one wavefront per row, lanes over columns)
+template <typename T, int NT>
+__device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int rows, int cols,
+                                        const T *x, T *y) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int r = w; r < rows; r += NW) {
+        T acc = 0;
+        for (int c = lane; c < cols; c += 64) acc += M[(size_t)r * ld + c] * x[c];
+        acc = wave_sum(acc);
+        if (lane == 0) y[r] = acc;
+    }
+}
+
+// y = U^T f, U upper triangular (incl. diagonal):  y[i] = sum_{j<=i} U[j][i] f[j]
+template <typename T, int NT>
+__device__ __forceinline__ void ut_mv(const T *U, int ld, int n, const T *f, T *y) {
+    for (int i = threadIdx.x; i < n; i += NT) {
+        T acc = 0;
+        for (int j = 0; j <= i; ++j) acc += U[(size_t)j * ld + i] * f[j];
+        y[i] = acc;
+    }
+}
+
+// x = U y:  x[j] = sum_{i>=j} U[j][i] y[i]   (wavefront per row)
+template <typename T, int NT>
+__device__ __forceinline__ void u_mv(const T *U, int ld, int n, const T *y, T *x) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int j = w; j < n; j += NW) {
+        T acc = 0;
+        for (int i = j + lane; i < n; i += 64) acc += U[(size_t)j * ld + i] * y[i];
+        acc = wave_sum(acc);
+        if (lane == 0) x[j] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky factorisation fused with the triangular inverse, in place.
+//
+// On entry the lower triangle (incl. diagonal) of H holds the SPD matrix and
+// its strict upper triangle is zero.  Right-looking: at step k, column k of L
+// is final; the trailing lower block is updated, and in the same pass row k of
+// X = L^{-1} (a forward substitution of L X = I carried for all right-hand
+// sides at once) updates the rows below it.  X is stored transposed in the
+// upper triangle (X[i][j] at H[j][i]), its diagonal in xd.  On exit the upper
+// triangle (incl. diagonal) holds U = L^{-T}.  Returns false (uniformly) on a
+// non-positive or non-finite pivot.
+template <typename T, int NT>
+__device__ bool chol_inv(T *H, int ld, int n, T *xd) {
+    const int tid = threadIdx.x;
+    for (int k = 0; k < n; ++k) {
+        const T dkk = H[(size_t)k * ld + k];
+        if (!(dkk > T(0)) || !isfinite(dkk)) return false;
+        const T inv = T(1) / sqrt(dkk);
+        // Phase A: scale column k of L (rows > k) and row k of X (H[j][k], j < k).
+        for (int i = tid; i < n; i += NT)
+            if (i != k) H[(size_t)i * ld + k] *= inv;
+        if (tid == 0) xd[k] = inv;
+        __syncthreads();
+        // Phase B over the rectangle rows (k, n) x columns [0, n), j <= i:
+        //   j >  k: L trailing update  H[i][j] -= L[i][k] L[j][k]
+        //   j <= k: X update           X[i][j] -= L[i][k] X[k][j]   (stored at H[j][i])
+        const int rows = n - k - 1;
+        const int total = rows * n;
+        for (int e = tid; e < total; e += NT) {
+            const int i = k + 1 + e / n, j = e % n;
+            if (j > i) continue;
+            const T lik = H[(size_t)i * ld + k];
+            if (j > k) {
+                H[(size_t)i * ld + j] -= lik * H[(size_t)j * ld + k];
+            } else {
+                const T xkj = (j < k) ? H[(size_t)j * ld + k] : xd[k];
+                H[(size_t)j * ld + i] -= lik * xkj;
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += NT) H[(size_t)i * ld + i] = xd[i];
+    __syncthreads();
+    return true;
+}
+
+// Reduced KKT solve with the stored inverse factors:
+//   [H A^T; A 0] [dz; dnu] = [f; r4]
+//   y = L^{-1} f;  dnu = S^{-1} (Wt y - r4);  dz = L^{-T} (y - Wt^T dnu)
+// y [n], t1/t2 [p] are scratch.  Results in dz [n], dnu [p].
+template <typename T, int NT>
+__device__ void kkt_solve(const T *U, int ldu, const T *Wt, const T *US, int n, int p,
+                          const T *f, const T *r4, T *y, T *t1, T *t2, T *dz, T *dnu) {
+    ut_mv<T, NT>(U, ldu, n, f, y);
+    __syncthreads();
+    if (p > 0) {
+        mv_rows<T, NT>(Wt, n, p, n, y, t1);
+        __syncthreads();
+        for (int k = threadIdx.x; k < p; k += NT) t1[k] -= r4[k];
+        __syncthreads();
+        ut_mv<T, NT>(US, p, p, t1, t2);
+        __syncthreads();
+        u_mv<T, NT>(US, p, p, t2, dnu);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) {
+            T acc = y[i];
+            for (int k = 0; k < p; ++k) acc -= Wt[(size_t)k * n + i] * dnu[k];
+            y[i] = acc;
+        }
+        __syncthreads();
+    }
+    u_mv<T, NT>(U, ldu, n, y, dz);
+    __syncthreads();
+}
+
+// H = Qs + G^T D G into the lower triangle of H (ld ldh), zero strict upper.
+template <typename T, int NT>
+__device__ void form_h(const T *__restrict__ Q, const T *__restrict__ G, const T *D, int n, int m,
+                       T *H, int ldh) {
+    const int total = n * n;
+    for (int e = threadIdx.x; e < total; e += NT) {
+        const int i = e / n, j = e % n;
+        if (j <= i) {
+            T acc = T(0.5) * (Q[(size_t)i * n + j] + Q[(size_t)j * n + i]);
+            for (int k = 0; k < m; ++k) acc += G[(size_t)k * n + i] * D[k] * G[(size_t)k * n + j];
+            H[(size_t)i * ldh + j] = acc;
+        } else {
+            H[(size_t)i * ldh + j] = T(0);
+        }
+    }
+    __syncthreads();
+}
+
+// Schur complement on A: Wt[k][:] = L^{-1} A[k][:]^T, S = Wt Wt^T into the lower
+// triangle of US (strict upper zeroed), then US <- LS^{-T} in place.
+template <typename T, int NT>
+__device__ bool schur(const T *U, int ldu, const T *__restrict__ A, int n, int p, T *Wt, T *US,
+                      T *xdp) {
+    const int tot = p * n;
+    for (int e = threadIdx.x; e < tot; e += NT) {
+        const int k = e / n, i = e % n;
+        T acc = 0;
+        for (int j = 0; j <= i; ++j) acc += U[(size_t)j * ldu + i] * A[(size_t)k * n + j];
+        Wt[(size_t)k * n + i] = acc;
+    }
+    __syncthreads();
+    const int tp = p * p;
+    for (int e = threadIdx.x; e < tp; e += NT) {
+        const int k = e / p, l = e % p;
+        T acc = 0;
+        if (l <= k)
+            for (int i = 0; i < n; ++i) acc += Wt[(size_t)k * n + i] * Wt[(size_t)l * n + i];
+        US[(size_t)k * p + l] = acc;
+    }
+    __syncthreads();
+    return chol_inv<T, NT>(US, p, p, xdp);
+}
+
+}  // namespace qpmi

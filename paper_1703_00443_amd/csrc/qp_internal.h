@@ -1,0 +1,90 @@
+// Internal launch interface between the C ABI (qp_api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qpmi.h"
+
+namespace qpmi {
+
+constexpr int kAlignBytes = 256;
+constexpr int kMaxNz = 1024;      // largest nz the kernels accept
+constexpr int kMaxNineq = 4096;   // largest nineq
+constexpr int kLdsLimit = 160 * 1024;
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Per-problem factor state, in elements of T, each region 256-byte aligned:
+//   U   [nz*nz]      upper triangle (incl. diagonal) = L^{-T}, L L^T = Qs + G^T D G
+//   D   [nineq]      lambda / s at the returned iterate
+//   Wt  [neq*nz]     Wt = (L^{-1} A^T)^T
+//   US  [neq*neq]    upper triangle = LS^{-T}, LS LS^T = Wt Wt^T (Schur complement)
+struct StateLayout {
+    size_t off_U, off_D, off_Wt, off_US, bytes;
+};
+
+__host__ __device__ inline StateLayout state_layout(int esz, int n, int m, int p) {
+    StateLayout s;
+    size_t o = 0;
+    s.off_U = o; o += align_up((size_t)n * n * esz, kAlignBytes);
+    s.off_D = o; o += align_up((size_t)(m > 0 ? m : 1) * esz, kAlignBytes);
+    s.off_Wt = o; o += align_up((size_t)(p > 0 ? p * n : 1) * esz, kAlignBytes);
+    s.off_US = o; o += align_up((size_t)(p > 0 ? p * p : 1) * esz, kAlignBytes);
+    s.bytes = o;
+    return s;
+}
+
+// Kernel-side description of one launch.  Either a uniform batch (desc == nullptr:
+// problem i at base + i*stride) or an uneven one (desc[order[i]]).
+struct FwdLaunch {
+    int count;
+    int nz, nineq, neq;                    // uniform mode
+    const void *Q, *q, *A, *b, *G, *h;     // uniform mode
+    int64_t sQ, sq, sA, sb, sG, sh;        // uniform mode
+    size_t state_stride;                   // uniform mode (bytes)
+    const qp_problem_desc *desc;           // varlen mode
+    const int32_t *order;                  // varlen mode (nullable)
+    const void *base_in;                   // varlen mode
+    void *z, *lam, *nu, *s;
+    char *state;
+    int32_t *status, *iters;
+    int max_iter;
+    double tol;
+    int lds_bytes;                         // dynamic LDS of the launch
+    int h_lds_budget;                      // bytes a problem may use for an LDS-resident factor
+    void *gscratch;                        // per-workgroup global scratch (vectors), nullable
+    size_t gscratch_stride;                // bytes per workgroup
+};
+
+struct BwdLaunch {
+    int count;
+    int nz, nineq, neq;
+    const void *Q, *q, *A, *b, *G, *h;
+    int64_t sQ, sq, sA, sb, sG, sh;
+    size_t state_stride;
+    const qp_problem_desc *desc;
+    const int32_t *need;
+    const void *base_in;
+    const void *z, *lam, *nu, *s;
+    const char *state;
+    const void *dl_dz;
+    // uniform-mode gradient outputs (nullable each)
+    void *dQ, *dq, *dA, *db, *dG, *dh;
+    // varlen-mode gradient base (inputs' offsets)
+    void *grad_base;
+    void *adj;                // [count * adj_stride] adjoint vectors (d_z, d_lam~, d_nu)
+    size_t adj_stride;        // elements per problem
+    int refine_steps;
+    int lds_bytes;
+    int max_rows;             // largest nz + nineq + neq + 1 of the launch
+};
+
+// Dynamic LDS bytes a problem's vectors need in the forward / backward kernels.
+size_t fwd_vec_lds_bytes(int esz, int n, int m, int p);
+size_t bwd_vec_lds_bytes(int esz, int n, int m, int p);
+size_t fwd_h_lds_bytes(int esz, int n);
+
+hipError_t launch_forward(qp_dtype dt, const FwdLaunch &L, hipStream_t st);
+hipError_t launch_backward(qp_dtype dt, const BwdLaunch &L, hipStream_t st);
+
+}  // namespace qpmi

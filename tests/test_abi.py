@@ -1,0 +1,143 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/qpmi.h declares, the ctypes structs match the C layout, and argument
+validation returns the documented error codes before any launch."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qpmi.h")
+
+
+def _lib():
+    from paper_1703_00443_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libqpmi.so not built")
+    return binding, binding.load_library()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\bint32_t\s+(qp_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    binding, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(binding.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    for name in names:
+        assert re.search(r"\bT %s\b" % name, out), name
+
+
+def test_struct_layout_matches_header():
+    binding, _ = _lib()
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "qpmi.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(qp_dims), sizeof(qp_opts), sizeof(qp_data),
+         sizeof(qp_problem_desc), offsetof(qp_opts, tol), offsetof(qp_opts, variant),
+         offsetof(qp_problem_desc, state));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "t")
+        subprocess.check_call(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), c, "-o", exe])
+        vals = list(map(int, subprocess.check_output([exe]).split()))
+    S = binding
+    assert vals == [ctypes.sizeof(S.qp_dims), ctypes.sizeof(S.qp_opts), ctypes.sizeof(S.qp_data),
+                    ctypes.sizeof(S.qp_problem_desc), S.qp_opts.tol.offset, S.qp_opts.variant.offset,
+                    S.qp_problem_desc.state.offset]
+
+
+def test_defaults_and_sizes():
+    binding, lib = _lib()
+    o = binding.qp_opts()
+    assert lib.qp_default_opts(binding.QP_F64, ctypes.byref(o)) == 0
+    assert (o.max_iter, o.refine_steps, o.tol) == (20, 1, 1e-8)
+    assert lib.qp_default_opts(binding.QP_F32, ctypes.byref(o)) == 0
+    assert (o.max_iter, o.refine_steps, o.tol) == (20, 3, 1e-3)
+    assert lib.qp_default_opts(7, ctypes.byref(o)) == binding.QP_EDTYPE
+    v = ctypes.c_size_t(0)
+    assert lib.qp_state_bytes(binding.QP_F64, binding.qp_dims(100, 100, 0), ctypes.byref(v)) == 0
+    assert v.value >= 100 * 100 * 8 + 100 * 8 and v.value % 256 == 0
+    for bad in ((0, 1, 0), (4, -1, 0), (4, 2, 4), (4, 2, -1)):
+        assert lib.qp_state_bytes(binding.QP_F64, binding.qp_dims(*bad), ctypes.byref(v)) == \
+            binding.QP_EARG
+    f, b = ctypes.c_size_t(1), ctypes.c_size_t(0)
+    assert lib.qp_workspace_query(binding.QP_F32, 128, binding.qp_dims(100, 100, 0),
+                                  ctypes.byref(o), ctypes.byref(f), ctypes.byref(b)) == 0
+    assert f.value == 0 and b.value >= 128 * 200 * 4
+    assert lib.qp_version() >= 100
+
+
+def test_forward_argument_errors_before_launch():
+    binding, lib = _lib()
+    o = binding.qp_opts()
+    lib.qp_default_opts(binding.QP_F64, ctypes.byref(o))
+    d = binding.qp_data()
+    dims = binding.qp_dims(4, 3, 1)
+    fake = ctypes.c_void_p(0x1000)
+    args = lambda data, opts, batch=2, dims=dims: (binding.QP_F64, batch, dims, data, opts, fake, fake,
+                                                   fake, fake, fake, fake, fake, None, 0, None)
+    # NULL data struct / NULL Q
+    assert lib.qp_forward_batched(*args(None, ctypes.byref(o))) == binding.QP_EARG
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(o))) == binding.QP_EARG
+    # inequality rows but no G
+    d.Q = d.q = d.A = d.b = 0x1000
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(o))) == binding.QP_EARG
+    d.G = d.h = 0x1000
+    # overlapping strides
+    d.sQ, d.sq, d.sA, d.sb, d.sG, d.sh = 3, 4, 4, 1, 12, 3
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(o))) == binding.QP_EARG
+    # bad options
+    d.sQ = 16
+    bad = binding.qp_opts()
+    lib.qp_default_opts(binding.QP_F64, ctypes.byref(bad))
+    bad.flags = 1
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(bad))) == binding.QP_EARG
+    bad.flags, bad.tol = 0, -1.0
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(bad))) == binding.QP_EARG
+    # bad dims / batch / dtype
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(o), dims=binding.qp_dims(4, 3, 4))) \
+        == binding.QP_EARG
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(o), batch=-1)) == binding.QP_EARG
+    assert lib.qp_forward_batched(9, 2, dims, ctypes.byref(d), ctypes.byref(o), fake, fake, fake, fake,
+                                  fake, fake, fake, None, 0, None) == binding.QP_EDTYPE
+    # empty batch is a no-op
+    assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(o), batch=0)) == binding.QP_OK
+
+
+def test_backward_workspace_too_small():
+    binding, lib = _lib()
+    o = binding.qp_opts()
+    lib.qp_default_opts(binding.QP_F64, ctypes.byref(o))
+    d = binding.qp_data()
+    d.Q = d.q = d.G = d.h = 0x1000
+    d.sQ, d.sq, d.sG, d.sh = 16, 4, 12, 3
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.qp_backward_batched(binding.QP_F64, 2, binding.qp_dims(4, 3, 0), ctypes.byref(d),
+                                 ctypes.byref(o), fake, fake, None, fake, fake, fake, fake, fake, None,
+                                 None, fake, fake, fake, 8, None)
+    assert rc == binding.QP_EWS
+
+
+def test_product_path_refuses_cpu_tensors():
+    import torch
+    binding, _ = _lib()
+    with pytest.raises(RuntimeError):
+        binding.make_problem(torch.eye(3, dtype=torch.float64), torch.zeros(3, dtype=torch.float64))

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Each problem's GPU step count is replayed by the oracle on the same (cast)
+inputs; z, lambda, nu and every gradient are compared element by element at
+the tolerances of tests/parity.py.
+"""
+import numpy as np
+import pytest
+
+from paper_1703_00443_amd import synth
+
+from parity import TOL_G, TOL_Z, g_err, grad_scale, oracle_grads, oracle_replay, z_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(batch, dtype, sample=None, need_grad=True, opts_over=None):
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(dtype))).to(dev)
+    n, m, p = batch.dims
+    prob = qb.make_problem(T(batch.Q), T(batch.q), T(batch.A) if p else None,
+                           T(batch.b) if p else None, T(batch.G) if m else None,
+                           T(batch.h) if m else None)
+    opts = qb.default_opts(tdt, **(opts_over or {}))
+    fw = qb.forward(prob, opts)
+    gr = qb.backward(prob, fw, T(batch.g), opts) if need_grad else None
+    torch.cuda.synchronize()
+    out = {k: getattr(fw, k).cpu().numpy() for k in ("z", "lam", "nu", "s", "status", "iters")}
+    if gr is not None:
+        for k in ("dQ", "dq", "dA", "db", "dG", "dh"):
+            v = getattr(gr, k)
+            out[k] = None if v is None else v.cpu().numpy()
+    return out
+
+
+def _check(batch, out, dtype, idx, need_grad=True):
+    n, m, p = batch.dims
+    for i in idx:
+        P = batch.problem(i)
+        st = int(out["status"][i])
+        assert st in (0, 1), "problem %d status %d" % (i, st)
+        r = oracle_replay(P, out["iters"][i], dtype)
+        ez = z_err(out["z"][i], r["z"])
+        assert ez <= TOL_Z[dtype], "problem %d: z err %.3e" % (i, ez)
+        if m:
+            assert z_err(out["s"][i], r["s"]) <= TOL_Z[dtype] * 10
+        if need_grad:
+            gref = oracle_grads(P, r, P["g"], dtype)
+            scale = grad_scale(gref)
+            for k in ("dQ", "dq", "dA", "db", "dG", "dh"):
+                if out.get(k) is None:
+                    continue
+                e = g_err(out[k][i], gref[k], scale)
+                assert e <= TOL_G[dtype], "problem %d %s: grad err %.3e" % (i, k, e)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_cpu_check_workload(dtype):
+    """8 problems, n=10, 20 inequalities, 5 equalities (every problem checked)."""
+    b = synth.make_batch(**synth.CPU_CHECK)
+    out = _run(b, dtype)
+    assert np.all(out["status"] == 0)
+    _check(b, out, dtype, range(8))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_paper_scale_sampled(dtype):
+    """128 problems, n=100, 100 inequalities, no equalities; 6 sampled problems."""
+    b = synth.make_batch(**synth.PAPER_SCALE)
+    out = _run(b, dtype)
+    assert np.all(out["status"] == 0), np.bincount(out["status"])
+    rng = np.random.default_rng(5)
+    _check(b, out, dtype, sorted(rng.choice(128, 6, replace=False)))
+
+
+@pytest.mark.parametrize("dims", [(17, 33, 3), (1, 2, 0), (5, 0, 2), (6, 0, 0), (33, 7, 0),
+                                  (64, 130, 9)])
+def test_ragged_and_degenerate_shapes(dims):
+    n, m, p = dims
+    b = synth.make_batch(seed=4242, B=3, n=n, m=m, p=p)
+    out = _run(b, np.float64)
+    _check(b, out, np.float64, range(3))
+    if m == 0:
+        assert np.all(out["iters"] == 0)
+
+
+def test_empty_batch():
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    dev = torch.device("cuda:0")
+    Q = torch.eye(3, dtype=torch.float64, device=dev).expand(0, 3, 3)
+    prob = qb.make_problem(Q, torch.zeros(0, 3, dtype=torch.float64, device=dev))
+    prob.batch = 0
+    fw = qb.forward(prob)
+    assert fw.z.shape == (0, 3)
+
+
+def test_shared_parameters_stride0():
+    """Q, G, A shared across the batch (stride 0), q, h, b per problem."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    b = synth.make_batch(seed=77, B=5, n=12, m=18, p=2)
+    dev = torch.device("cuda:0")
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    prob = qb.make_problem(T(b.Q[0]), T(b.q), T(b.A[0]), T(b.b), T(b.G[0]), T(b.h))
+    fw = qb.forward(prob)
+    torch.cuda.synchronize()
+    z, iters = fw.z.cpu().numpy(), fw.iters.cpu().numpy()
+    for i in range(5):
+        P = {"Q": b.Q[0], "q": b.q[i], "A": b.A[0], "b": b.b[i], "G": b.G[0], "h": b.h[i]}
+        r = oracle_replay(P, iters[i], np.float64)
+        assert z_err(z[i], r["z"]) <= TOL_Z[np.float64]
+
+
+def test_status_codes():
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    dev = torch.device("cuda:0")
+    b = synth.make_batch(seed=9, B=3, n=6, m=8, p=1)
+    Q = b.Q.copy()
+    q = b.q.copy()
+    q[1, 0] = np.nan            # problem 1: non-finite input
+    Q[2] = -np.eye(6)           # problem 2: negative definite -> factorization breakdown
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    prob = qb.make_problem(T(Q), T(q), T(b.A), T(b.b), T(b.G), T(b.h))
+    fw = qb.forward(prob)
+    st = fw.status.cpu().numpy()
+    assert st[0] == 0 and st[1] == 3 and st[2] == 2, st
+
+
+def test_deterministic_rerun():
+    b = synth.make_batch(**dict(synth.CPU_CHECK, B=4))
+    o1 = _run(b, np.float64)
+    o2 = _run(b, np.float64)
+    for k in ("z", "lam", "nu", "dQ", "dG"):
+        np.testing.assert_array_equal(o1[k], o2[k])
+
+
+def test_generic_variant_matches_lds_variant_bitwise():
+    """The factor-in-global-memory variant runs the same arithmetic in the same
+    order as the LDS-resident one."""
+    from paper_1703_00443_amd import binding as qb
+    b = synth.make_batch(**dict(synth.CPU_CHECK, B=3))
+    o1 = _run(b, np.float64)
+    o2 = _run(b, np.float64, opts_over={"variant": qb.VARIANT_GENERIC})
+    for k in ("z", "lam", "nu", "iters", "dQ", "dG", "dA"):
+        np.testing.assert_array_equal(o1[k], o2[k])
