@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Throughput of the batched QP layer (forward + backward) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
+
+A step is one forward solve (primal-dual interior point method, Section 3.1)
+plus one backward pass (eq. grads-system / eq. grads) over one batch of the
+paper-scale workload: 128 random feasible QPs with nz = 100 variables,
+nineq = 100 inequalities, neq = 0 (the timing experiment of Section 5.1),
+drawn by paper_1703_00443_amd.synth with row-normalised G.  Inputs are resident
+in HBM before the timed region.  Prints one JSON line.
+
+Besides the headline number the line carries:
+  roofline      forward kernel: algorithmic flops per launch / measured kernel time
+  cpu_baseline  the FP64 oracle on the host's cores over a bounded sample
+  plain         the same library called once per QP (batch 1, host sync per call)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QP solves/s fwd+bwd (B=128,n=m=100) vs plain; p50/p99 latency in serving"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X published dense peaks (vector = matrix)
+HBM_GBS = 8000.0
+KERNEL_SOURCES = ("qp_core.hpp", "qp_forward.hip", "qp_tiled.hpp")
+
+
+def algorithmic_flops(n, m, p, iters):
+    """Flops the method needs for one QP that took `iters` Newton steps
+    (matrix products counted once for symmetric results):
+      factorisation of an iterate: H = Qs + G^T D G  n(n+1)m, Cholesky n^3/3,
+        Schur complement n^2 p + n p (p+1) + p^3/3;
+      residuals: 2n^2 + 4nm + 4np;  one reduced solve: 4nm + 2n^2 + 4np + 2p^2.
+    The forward factors iters + 2 times (initial point, every iterate incl. the
+    returned one), forms residuals iters + 1 times and solves 2 iters + 1 times."""
+    fac = n * (n + 1) * m + n ** 3 / 3.0 + (n * n * p + n * p * (p + 1) + p ** 3 / 3.0 if p else 0.0)
+    res = 2 * n * n + 4 * n * m + 4 * n * p
+    sol = 4 * n * m + 2 * n * n + 4 * n * p + 2 * p * p
+    it = np.asarray(iters, dtype=np.float64)
+    return float(np.sum(fac * (it + 2) + res * (it + 1) + sol * (2 * it + 1)))
+
+
+def backward_bytes(n, m, p, esz):
+    """Algorithmic HBM bytes of one backward: read Q, G, A, z, lam, nu, s, dl/dz and
+    the stored factor (U n^2, D m, Wt pn, US p^2); write every gradient."""
+    rd = n * n + m * n + p * n + n + 2 * m + p + n + (n * n + m + p * n + p * p)
+    wr = n * n + n + p * n + p + m * n + m
+    return (rd + wr) * esz
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        path = os.path.join(ROOT, "paper_1703_00443_amd", "csrc", f)
+        if os.path.exists(path):
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(dtype, launches_bytes):
+    """HBM traffic of the forward kernel from committed rocprofv3 counter
+    summaries, only if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "qp_forward_paper_scale_%s_counters.json" % dtype)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(batch_np, target_cpu_s=12.0):
+    """The FP64 oracle (as it stands) on the host cores over a bounded sample
+    of the same workload: forward + backward per problem."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    threads = max(1, min(16, os.cpu_count() or 1))
+    B = batch_np.q.shape[0]
+
+    def one(i):
+        P = batch_np.problem(i % B)
+        r = oracle.solve(P["Q"], P["q"], P["A"], P["b"], P["G"], P["h"])
+        oracle.backward(P["Q"], P["A"], P["G"], P["h"], r["z"], r["lam"], r["nu"], P["g"])
+        return r["iters"]
+
+    t0 = time.perf_counter()
+    one(0)
+    t_one = time.perf_counter() - t0
+    count = int(max(threads, min(4 * B, round(target_cpu_s / max(t_one, 1e-4)))))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one, range(count)))
+    el = time.perf_counter() - t0
+    return {"value": count / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": "%d fwd+bwd solves (problems 0..%d of the same batch, cycled), FP64, "
+                      "one QP per thread" % (count, min(count, B) - 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every QP is independent and this build runs on a "
+              "single MI355X (see DESIGN.md for how the batch would shard); got --gpus %d"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(3)
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    npdt = np.float64 if args.dtype == "f64" else np.float32
+    cfg = synth.PAPER_SCALE
+    bnp = synth.make_batch(**cfg)
+    B, n, m, p = cfg["B"], cfg["n"], cfg["m"], cfg["p"]
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(npdt))).to(dev)
+    prob = qb.make_problem(T(bnp.Q), T(bnp.q), None, None, T(bnp.G), T(bnp.h))
+    g = T(bnp.g)
+    opts = qb.default_opts(tdt)
+    fw = qb.forward(prob, opts)
+    _, bws = qb.workspace_bytes(tdt, B, n, m, p, opts)
+    ws = torch.empty(bws, dtype=torch.uint8, device=dev)
+    gr = qb.backward(prob, fw, g, opts, ws=ws)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        qb.forward(prob, opts, out=fw)
+        qb.backward(prob, fw, g, opts, ws=ws)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        qb.forward(prob, opts, out=fw)
+        ev[k][1].record(stream)
+        qb.backward(prob, fw, g, opts, ws=ws)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    bwd_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    iters = fw.iters.cpu().numpy()
+    status = fw.status.cpu().numpy()
+    value = B * args.steps / el
+
+    flops = algorithmic_flops(n, m, p, iters)
+    achieved = flops / (fwd_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.dtype]
+    esz = 8 if args.dtype == "f64" else 4
+    traffic = traffic_from_profiles(args.dtype, None)
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic (seeded generator of the paper's timing experiment)",
+        "config": {"workload": "paper-scale batch: 128 QPs, nz=100, nineq=100, neq=0, "
+                               "row-normalised G, fwd+bwd",
+                   "batch": B, "nz": n, "nineq": m, "neq": p,
+                   "tol": opts.tol, "max_iter": opts.max_iter, "refine_steps": opts.refine_steps},
+        "roofline": {"kernel": "qp_forward_kernel", "bound": "alu", "achieved": round(achieved, 4),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                     "traffic": traffic,
+                     "flops_per_launch": flops, "launch_ms": round(fwd_ms, 4)},
+        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+        "bwd_hbm_gbs": round(B * backward_bytes(n, m, p, esz) / (bwd_ms * 1e-3) / 1e9, 2),
+        "iters_mean": float(iters.mean()), "status_counts": np.bincount(status, minlength=4).tolist(),
+    }
+
+    if not args.no_plain:
+        # the same library called once per QP with a host sync per call
+        singles = [qb.make_problem(prob.Q[i:i + 1], prob.q[i:i + 1], None, None, prob.G[i:i + 1],
+                                   prob.h[i:i + 1]) for i in range(B)]
+        f1 = qb.forward(singles[0], opts)
+        ws1 = torch.empty(qb.workspace_bytes(tdt, 1, n, m, p, opts)[1], dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(B):
+            qb.forward(singles[i], opts, out=f1)
+            qb.backward(singles[i], f1, g[i:i + 1], opts, ws=ws1)
+            torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        out["plain"] = {"value": round(B / pel, 2), "unit": "solves/s",
+                        "how": "batch-1 calls of the same library, 128 sequential fwd+bwd, host sync "
+                               "per call"}
+        out["speedup_vs_plain"] = round(value / (B / pel), 2)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(bnp)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,15 +32,6 @@ static int device_lds_limit() {
     return cached;
 }
 
-// Dynamic LDS of a forward launch over problems whose largest dims are given:
-// the vectors always, plus the factor when it fits next to them.
-static void fwd_lds_plan(int esz, int n, int m, int p, int *lds_bytes, int *h_budget) {
-    const int lim = device_lds_limit();
-    const size_t vec = fwd_vec_lds_bytes(esz, n, m, p);
-    const size_t hb = fwd_h_lds_bytes(esz, n);
-    *h_budget = lim;
-    *lds_bytes = (int)((vec + hb <= (size_t)lim) ? vec + hb : vec);
-}
 
 extern "C" {
 
@@ -126,7 +117,9 @@ int32_t qp_forward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_da
     if (d.nineq > 0 && (!lam || !s)) return QP_EARG;
     if (d.neq > 0 && !nu) return QP_EARG;
     const int esz = esize(dtype);
-    if (fwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq) > (size_t)device_lds_limit()) return QP_ETOOBIG;
+    const int lim = device_lds_limit();
+    int lds = 0;
+    if (fwd_plan(esz, d.nz, d.nineq, d.neq, opts->variant, lim, &lds) == kPolicyNone) return QP_ETOOBIG;
 
     FwdLaunch L;
     memset(&L, 0, sizeof(L));
@@ -140,11 +133,9 @@ int32_t qp_forward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_da
     L.status = status; L.iters = iters;
     L.max_iter = opts->max_iter;
     L.tol = opts->tol;
-    fwd_lds_plan(esz, d.nz, d.nineq, d.neq, &L.lds_bytes, &L.h_lds_budget);
-    if (opts->variant == QP_VARIANT_GENERIC) {
-        L.lds_bytes = (int)fwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq);
-        L.h_lds_budget = 0;
-    }
+    L.lds_bytes = lds;
+    L.lds_limit = lim;
+    L.variant = opts->variant;
     return hip_ret(launch_forward(dtype, L, (hipStream_t)stream));
 }
 
@@ -230,17 +221,15 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
     if (!desc_dev || !desc_host || !base_in || !z || !lam || !nu || !s || !state || !status || !iters)
         return QP_EARG;
     const int esz = esize(dtype);
-    int mn = 1, mm = 0, mp = 0;
-    int lds = 0, budget = 0;
+    const int lim = device_lds_limit();
+    int lds = 0;
     for (int i = 0; i < count; ++i) {
         const qp_problem_desc &d = desc_host[i];
         if (!desc_ok(d)) return QP_EARG;
-        if (fwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq) > (size_t)device_lds_limit()) return QP_ETOOBIG;
-        int l, b;
-        fwd_lds_plan(esz, d.nz, d.nineq, d.neq, &l, &b);
+        const int var = d.variant ? d.variant : opts->variant;
+        int l = 0;
+        if (fwd_plan(esz, d.nz, d.nineq, d.neq, var, lim, &l) == kPolicyNone) return QP_ETOOBIG;
         lds = std::max(lds, l);
-        budget = b;
-        mn = std::max(mn, d.nz); mm = std::max(mm, d.nineq); mp = std::max(mp, d.neq);
     }
     FwdLaunch L;
     memset(&L, 0, sizeof(L));
@@ -254,8 +243,8 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
     L.max_iter = opts->max_iter;
     L.tol = opts->tol;
     L.lds_bytes = lds;
-    L.h_lds_budget = budget;
-    if (opts->variant == QP_VARIANT_GENERIC) L.h_lds_budget = 0;
+    L.lds_limit = lim;
+    L.variant = opts->variant;
     return hip_ret(launch_forward(dtype, L, (hipStream_t)stream));
 }
 

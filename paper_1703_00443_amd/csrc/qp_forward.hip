@@ -1,338 +1,73 @@
-// Forward kernel: the primal-dual interior point method of Section 3.1 for a
-// batch of QPs, one workgroup per problem, the whole solve (initial point,
-// Newton loop, stored factor) in one launch.
-//
-// Per iterate (order chosen so that the factor kept for the backward pass is
-// the one of the returned iterate):
-//   residuals r_x, r_s, r_y and mu = s^T lambda / nineq        (KKT conditions)
-//   D = lambda / s,  H = Qs + G^T D G,  H = L L^T (+ inverse)  (symmetrised K)
-//   Schur complement on A if neq > 0
-//   stop test
-//   affine direction (eq. cvxgen:affine), step to the boundary, mu_aff,
-//   sigma = (mu_aff / mu)^3, centering-plus-corrector direction
-//   (eq. cvxgen:cc) with the same factor, combined step with 0.99 of the
-//   step to the boundary (capped at 1), update of (z, s, lambda, nu).
-#include "qp_core.hpp"
+// Forward kernel: the interior point method of Section 3.1 for a batch of
+// QPs, one workgroup (256 threads) per problem, the whole solve (initial point,
+// Newton loop, stored factor) in one launch.  Each workgroup picks the
+// factorization policy of its problem from the problem's own dims.
+#include "qp_policies.hpp"
 
 namespace qpmi {
 
-template <typename T>
-struct Prob {
-    int n, m, p;
-    const T *Q, *q, *A, *b, *G, *h;
-    T *z, *lam, *nu, *s;
-    char *state;
-    int out;  // index into status / iters
-};
+constexpr int kFwdThreads = 64 * kTiledWaves;
 
-template <typename T>
-__device__ __forceinline__ Prob<T> fwd_problem(const FwdLaunch &L, int idx) {
-    Prob<T> P;
-    if (L.desc == nullptr) {
-        const int j = idx;
-        P.n = L.nz; P.m = L.nineq; P.p = L.neq;
-        P.Q = (const T *)L.Q + (size_t)j * L.sQ;
-        P.q = (const T *)L.q + (size_t)j * L.sq;
-        P.A = (const T *)L.A + (size_t)j * L.sA;
-        P.b = (const T *)L.b + (size_t)j * L.sb;
-        P.G = (const T *)L.G + (size_t)j * L.sG;
-        P.h = (const T *)L.h + (size_t)j * L.sh;
-        P.z = (T *)L.z + (size_t)j * P.n;
-        P.lam = (T *)L.lam + (size_t)j * P.m;
-        P.s = (T *)L.s + (size_t)j * P.m;
-        P.nu = (T *)L.nu + (size_t)j * P.p;
-        P.state = L.state + (size_t)j * L.state_stride;
-        P.out = j;
-    } else {
-        const int j = L.order ? L.order[idx] : idx;
-        const qp_problem_desc d = L.desc[j];
-        const T *base = (const T *)L.base_in;
-        P.n = d.nz; P.m = d.nineq; P.p = d.neq;
-        P.Q = base + d.Q; P.q = base + d.q; P.A = base + d.A;
-        P.b = base + d.b; P.G = base + d.G; P.h = base + d.h;
-        P.z = (T *)L.z + d.z; P.lam = (T *)L.lam + d.lam; P.s = (T *)L.s + d.lam;
-        P.nu = (T *)L.nu + d.nu;
-        P.state = L.state + d.state;
-        P.out = j;
+__host__ __device__ inline int plan_policy(int esz, int n, int m, int p, int variant, int lds_limit,
+                                           int *lds_bytes) {
+    const int base = IpmLayout(n, m, p).end;
+    if ((variant == QP_VARIANT_AUTO || variant == QP_VARIANT_TILED) && p == 0 && n <= kTiledMaxN) {
+        const int gl = TiledLayout<true>(base, n, m).end * esz;
+        if (gl <= lds_limit) { *lds_bytes = gl; return kPolicyTiledGLds; }
+        const int gg = TiledLayout<false>(base, n, m).end * esz;
+        if (gg <= lds_limit) { *lds_bytes = gg; return kPolicyTiledGGlobal; }
     }
-    return P;
+    if (variant != QP_VARIANT_GENERIC) {
+        const int hl = GenericLayout<true>(base, n, m, p).end * esz;
+        if (hl <= lds_limit) { *lds_bytes = hl; return kPolicyGenericLds; }
+    }
+    const int gg = GenericLayout<false>(base, n, m, p).end * esz;
+    if (gg <= lds_limit) { *lds_bytes = gg; return kPolicyGenericGlobal; }
+    *lds_bytes = gg;
+    return kPolicyNone;
 }
 
-// LDS vector layout of the forward kernel, in elements of T.
-struct FwdLayout {
-    int z, rx, f, y, dza, dzc, tn, tn2, xd;           // n-vectors
-    int s, lam, rz, D, dsa, dla, dsc, dlc, w, tm;     // m-vectors
-    int nu, ry, dna, dnc, tp, tp2, xdp;               // p-vectors
-    int red;                                          // 64 reduction slots
-    int H;                                            // start of an LDS-resident factor
-    __host__ __device__ FwdLayout(int n, int m, int p) {
-        const int N = pad4(n), M = pad4(m), Pp = pad4(p);
-        int o = 0;
-        z = o; o += N; rx = o; o += N; f = o; o += N; y = o; o += N; dza = o; o += N;
-        dzc = o; o += N; tn = o; o += N; tn2 = o; o += N; xd = o; o += N;
-        s = o; o += M; lam = o; o += M; rz = o; o += M; D = o; o += M; dsa = o; o += M;
-        dla = o; o += M; dsc = o; o += M; dlc = o; o += M; w = o; o += M; tm = o; o += M;
-        nu = o; o += Pp; ry = o; o += Pp; dna = o; o += Pp; dnc = o; o += Pp; tp = o; o += Pp;
-        tp2 = o; o += Pp; xdp = o; o += Pp;
-        red = o; o += 64;
-        H = o;
-    }
-};
-
-__host__ __device__ inline int h_ld(int n) { return n | 1; }
-
-size_t fwd_vec_lds_bytes(int esz, int n, int m, int p) { return (size_t)FwdLayout(n, m, p).H * esz; }
-size_t fwd_h_lds_bytes(int esz, int n) { return (size_t)n * h_ld(n) * esz; }
-
-template <typename T, int NT, bool HL>
-__device__ void solve_one(const Prob<T> &P, T *sm, const FwdLayout &Lo, int max_iter, T tol,
-                          int32_t *status, int32_t *iters) {
-    const int n = P.n, m = P.m, p = P.p;
-    const int tid = threadIdx.x;
-    const StateLayout SL = state_layout(sizeof(T), n, m, p);
-    T *U_state = (T *)(P.state + SL.off_U);
-    T *Dst = (T *)(P.state + SL.off_D);
-    T *Wt = (T *)(P.state + SL.off_Wt);
-    T *US = (T *)(P.state + SL.off_US);
-    T *H;
-    int ldh;
-    if (HL) { H = sm + Lo.H; ldh = h_ld(n); } else { H = U_state; ldh = n; }
-
-    T *z = sm + Lo.z, *rx = sm + Lo.rx, *f = sm + Lo.f, *y = sm + Lo.y, *dza = sm + Lo.dza,
-      *dzc = sm + Lo.dzc, *tn = sm + Lo.tn, *tn2 = sm + Lo.tn2, *xd = sm + Lo.xd;
-    T *s = sm + Lo.s, *lam = sm + Lo.lam, *rz = sm + Lo.rz, *D = sm + Lo.D, *dsa = sm + Lo.dsa,
-      *dla = sm + Lo.dla, *dsc = sm + Lo.dsc, *dlc = sm + Lo.dlc, *w = sm + Lo.w, *tm = sm + Lo.tm;
-    T *nu = sm + Lo.nu, *ry = sm + Lo.ry, *dna = sm + Lo.dna, *dnc = sm + Lo.dnc,
-      *tp = sm + Lo.tp, *tp2 = sm + Lo.tp2, *xdp = sm + Lo.xdp;
-    T *red = sm + Lo.red;
-
-    const T *__restrict__ Q = P.Q;
-    const T *__restrict__ G = P.G;
-    const T *__restrict__ A = P.A;
-
-    // Input finiteness (one pass over every input).
-    bool fin = true;
-    for (int e = tid; e < n * n; e += NT) fin &= isfinite(Q[e]);
-    for (int e = tid; e < m * n; e += NT) fin &= isfinite(G[e]);
-    for (int e = tid; e < p * n; e += NT) fin &= isfinite(A[e]);
-    for (int e = tid; e < n; e += NT) fin &= isfinite(P.q[e]);
-    for (int e = tid; e < m; e += NT) fin &= isfinite(P.h[e]);
-    for (int e = tid; e < p; e += NT) fin &= isfinite(P.b[e]);
-    {
-        T bad = fin ? T(0) : T(1), d0 = 0, d1 = 0;
-        block_reduce3<T, NT>(bad, d0, d1, red);
-        fin = bad == T(0);
-    }
-    int st = QP_STATUS_MAX_ITER, it = 0;
-    if (!fin) {
-        st = QP_STATUS_NONFINITE;
-        for (int e = tid; e < n; e += NT) z[e] = 0;
-        for (int e = tid; e < m; e += NT) { s[e] = 0; lam[e] = 0; D[e] = 0; }
-        for (int e = tid; e < p; e += NT) nu[e] = 0;
-        __syncthreads();
-        goto finish;
-    }
-
-    // ---- initial point: K with the (D(lambda), D(s)) pair replaced by (I, I)
-    for (int e = tid; e < m; e += NT) D[e] = T(1);
-    __syncthreads();
-    {
-        form_h<T, NT>(Q, G, D, n, m, H, ldh);
-        bool ok = chol_inv<T, NT>(H, ldh, n, xd);
-        if (ok && p > 0) ok = schur<T, NT>(H, ldh, A, n, p, Wt, US, xdp);
-        if (!ok) {
-            st = QP_STATUS_BREAKDOWN;
-            for (int e = tid; e < n; e += NT) z[e] = 0;
-            for (int e = tid; e < m; e += NT) { s[e] = 0; lam[e] = 0; }
-            for (int e = tid; e < p; e += NT) nu[e] = 0;
-            __syncthreads();
-            goto finish;
-        }
-        // f = -q + G^T h  (r1 = -q, r2 = 0, r3 = h, r4 = b)
-        mv_cols<T, NT>(G, n, m, n, P.h, f);
-        __syncthreads();
-        for (int i = tid; i < n; i += NT) f[i] -= P.q[i];
-        for (int k = tid; k < p; k += NT) tp2[k] = P.b[k];
-        __syncthreads();
-        kkt_solve<T, NT>(H, ldh, Wt, US, n, p, f, tp2, y, tp, tn2, z, nu);
-        if (m > 0) {
-            mv_rows<T, NT>(G, n, m, n, z, tm);
-            __syncthreads();
-            T mns = pinf<T>(), mnl = pinf<T>(), dummy = 0;
-            for (int k = tid; k < m; k += NT) {
-                const T sk = P.h[k] - tm[k];
-                s[k] = sk;
-                lam[k] = -sk;
-                mns = fmin(mns, sk);
-                mnl = fmin(mnl, -sk);
-            }
-            T mx = -pinf<T>();
-            block_reduce3<T, NT>(dummy, mx, mns, red);
-            dummy = 0; mx = -pinf<T>();
-            block_reduce3<T, NT>(dummy, mx, mnl, red);
-            for (int k = tid; k < m; k += NT) {
-                if (mns <= T(0)) s[k] += T(1) - mns;
-                if (mnl <= T(0)) lam[k] += T(1) - mnl;
-            }
-            __syncthreads();
-        } else {
-            st = QP_STATUS_OPTIMAL;
-            goto store_factor;
-        }
-    }
-
-    // ---- Newton loop
-    for (it = 0;; ++it) {
-        // residuals: rx = -(Qs z + q + G^T lam + A^T nu), rz = -(G z + s - h), ry = -(A z - b)
-        mv_rows<T, NT>(Q, n, n, n, z, tn);    // Q z
-        mv_cols<T, NT>(Q, n, n, n, z, tn2);   // Q^T z
-        mv_rows<T, NT>(G, n, m, n, z, tm);    // G z
-        mv_cols<T, NT>(G, n, m, n, lam, rx);  // G^T lam
-        if (p > 0) {
-            mv_rows<T, NT>(A, n, p, n, z, ry);  // A z
-            mv_cols<T, NT>(A, n, p, n, nu, f);  // A^T nu
-        }
-        __syncthreads();
-        T vsum = 0, vmax = 0, vmin = pinf<T>();
-        for (int i = tid; i < n; i += NT) {
-            T acc = T(0.5) * (tn[i] + tn2[i]) + P.q[i] + rx[i];
-            if (p > 0) acc += f[i];
-            rx[i] = -acc;
-            vmax = fmax(vmax, fabs(acc));
-            vmin = fmin(vmin, isfinite(acc) ? T(1) : T(0));
-        }
-        for (int k = tid; k < m; k += NT) {
-            const T r = -(tm[k] + s[k] - P.h[k]);
-            rz[k] = r;
-            vmax = fmax(vmax, fabs(r));
-            vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
-            vsum += s[k] * lam[k];
-            D[k] = lam[k] / s[k];
-        }
-        for (int k = tid; k < p; k += NT) {
-            const T r = -(ry[k] - P.b[k]);
-            ry[k] = r;
-            vmax = fmax(vmax, fabs(r));
-            vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
-        }
-        block_reduce3<T, NT>(vsum, vmax, vmin, red);
-        const T mu = vsum / T(m);
-        const T err = fmax(mu, vmax);
-        const bool finite_now = vmin > T(0) && isfinite(mu);
-
-        // factor at this iterate
-        form_h<T, NT>(Q, G, D, n, m, H, ldh);
-        bool ok = finite_now && chol_inv<T, NT>(H, ldh, n, xd);
-        if (ok && p > 0) ok = schur<T, NT>(H, ldh, A, n, p, Wt, US, xdp);
-
-        if (!finite_now) { st = QP_STATUS_NONFINITE; break; }
-        if (!ok) { st = QP_STATUS_BREAKDOWN; break; }
-        if (err <= tol) { st = QP_STATUS_OPTIMAL; break; }
-        if (it >= max_iter) { st = QP_STATUS_MAX_ITER; break; }
-
-        // ---- affine direction: f = rx + G^T (lam + D rz), r4 = ry
-        for (int k = tid; k < m; k += NT) tm[k] = lam[k] + D[k] * rz[k];
-        __syncthreads();
-        mv_cols<T, NT>(G, n, m, n, tm, f);
-        __syncthreads();
-        for (int i = tid; i < n; i += NT) f[i] += rx[i];
-        __syncthreads();
-        kkt_solve<T, NT>(H, ldh, Wt, US, n, p, f, ry, y, tp, tp2, dza, dna);
-        mv_rows<T, NT>(G, n, m, n, dza, tm);
-        __syncthreads();
-        T amin = pinf<T>(), d0 = 0, d1 = 0;
-        for (int k = tid; k < m; k += NT) {
-            const T ds = rz[k] - tm[k];
-            const T dl = -lam[k] - D[k] * ds;
-            dsa[k] = ds;
-            dla[k] = dl;
-            if (ds < T(0)) amin = fmin(amin, -s[k] / ds);
-            if (dl < T(0)) amin = fmin(amin, -lam[k] / dl);
-        }
-        block_reduce3<T, NT>(d0, d1, amin, red);
-        const T a_aff = fmin(T(1), amin);
-        T msum = 0;
-        for (int k = tid; k < m; k += NT) msum += (s[k] + a_aff * dsa[k]) * (lam[k] + a_aff * dla[k]);
-        msum = block_sum<T, NT>(msum, red);
-        const T mu_aff = msum / T(m);
-        const T ratio = mu_aff / mu;
-        const T sigma = ratio * ratio * ratio;
-
-        // ---- centering-plus-corrector: w = (sigma mu - dsa dla) / s, f = -G^T w, r4 = 0
-        for (int k = tid; k < m; k += NT) w[k] = (sigma * mu - dsa[k] * dla[k]) / s[k];
-        for (int k = tid; k < p; k += NT) tn2[k] = T(0);  // r4 = 0 (tn2 reused as p-scratch)
-        __syncthreads();
-        mv_cols<T, NT>(G, n, m, n, w, f);
-        __syncthreads();
-        for (int i = tid; i < n; i += NT) f[i] = -f[i];
-        __syncthreads();
-        kkt_solve<T, NT>(H, ldh, Wt, US, n, p, f, tn2, y, tp, tp2, dzc, dnc);
-        mv_rows<T, NT>(G, n, m, n, dzc, tm);
-        __syncthreads();
-        amin = pinf<T>(); d0 = 0; d1 = 0;
-        for (int k = tid; k < m; k += NT) {
-            const T dsc_k = -tm[k];
-            const T dlc_k = w[k] - D[k] * dsc_k;
-            const T ds = dsa[k] + dsc_k;
-            const T dl = dla[k] + dlc_k;
-            dsc[k] = ds;
-            dlc[k] = dl;
-            if (ds < T(0)) amin = fmin(amin, -s[k] / ds);
-            if (dl < T(0)) amin = fmin(amin, -lam[k] / dl);
-        }
-        block_reduce3<T, NT>(d0, d1, amin, red);
-        const T alpha = fmin(T(1), T(0.99) * amin);
-        for (int i = tid; i < n; i += NT) z[i] += alpha * (dza[i] + dzc[i]);
-        for (int k = tid; k < m; k += NT) { s[k] += alpha * dsc[k]; lam[k] += alpha * dlc[k]; }
-        for (int k = tid; k < p; k += NT) nu[k] += alpha * (dna[k] + dnc[k]);
-        __syncthreads();
-    }
-
-store_factor:
-    if (HL) {
-        for (int e = tid; e < n * n; e += NT) {
-            const int i = e / n, j = e % n;
-            U_state[e] = H[(size_t)i * ldh + j];
-        }
-    }
-    for (int k = tid; k < m; k += NT) Dst[k] = D[k];
-
-finish:
-    for (int i = tid; i < n; i += NT) P.z[i] = z[i];
-    for (int k = tid; k < m; k += NT) { P.s[k] = s[k]; P.lam[k] = lam[k]; }
-    for (int k = tid; k < p; k += NT) P.nu[k] = nu[k];
-    if (tid == 0) { status[P.out] = st; iters[P.out] = it; }
-    __syncthreads();
+int fwd_plan(int esz, int n, int m, int p, int variant, int lds_limit, int *lds_bytes) {
+    return plan_policy(esz, n, m, p, variant, lds_limit, lds_bytes);
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void qp_forward_kernel(FwdLaunch L) {
+template <typename T>
+__global__ __launch_bounds__(kFwdThreads) void qp_forward_kernel(FwdLaunch L) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
+    const T tol = (T)L.tol;
     for (int idx = blockIdx.x; idx < L.count; idx += gridDim.x) {
         const Prob<T> P = fwd_problem<T>(L, idx);
-        const FwdLayout Lo(P.n, P.m, P.p);
-        const size_t need = (size_t)Lo.H * sizeof(T) + (size_t)P.n * h_ld(P.n) * sizeof(T);
-        if (need <= (size_t)L.h_lds_budget && need <= (size_t)L.lds_bytes)
-            solve_one<T, NT, true>(P, sm, Lo, L.max_iter, (T)L.tol, L.status, L.iters);
-        else
-            solve_one<T, NT, false>(P, sm, Lo, L.max_iter, (T)L.tol, L.status, L.iters);
+        const IpmLayout Lo(P.n, P.m, P.p);
+        int bytes = 0;
+        const int pol = plan_policy(sizeof(T), P.n, P.m, P.p, P.variant, L.lds_limit, &bytes);
+        if (pol == kPolicyTiledGLds) {
+            TiledFactor<T, true> f(P, sm, Lo.end);
+            ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, tol, L.status, L.iters);
+        } else if (pol == kPolicyTiledGGlobal) {
+            TiledFactor<T, false> f(P, sm, Lo.end);
+            ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, tol, L.status, L.iters);
+        } else if (pol == kPolicyGenericLds) {
+            GenericFactor<T, kFwdThreads, true> f(P, sm, Lo.end);
+            ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, tol, L.status, L.iters);
+        } else {
+            GenericFactor<T, kFwdThreads, false> f(P, sm, Lo.end);
+            ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, tol, L.status, L.iters);
+        }
     }
 }
-
-constexpr int kFwdThreads = 256;
 
 template <typename T>
 static hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
     if (L.count <= 0) return hipSuccess;
-    auto kern = qp_forward_kernel<T, kFwdThreads>;
+    auto kern = qp_forward_kernel<T>;
     static bool attr_done = false;
     if (!attr_done) {
-        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  L.lds_limit);
         attr_done = true;
     }
-    int grid = L.count;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kFwdThreads), L.lds_bytes, st, L);
+    hipLaunchKernelGGL(kern, dim3(L.count), dim3(kFwdThreads), L.lds_bytes, st, L);
     return hipGetLastError();
 }
 

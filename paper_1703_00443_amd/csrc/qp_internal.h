@@ -50,10 +50,9 @@ struct FwdLaunch {
     int32_t *status, *iters;
     int max_iter;
     double tol;
-    int lds_bytes;                         // dynamic LDS of the launch
-    int h_lds_budget;                      // bytes a problem may use for an LDS-resident factor
-    void *gscratch;                        // per-workgroup global scratch (vectors), nullable
-    size_t gscratch_stride;                // bytes per workgroup
+    int lds_bytes;                         // dynamic LDS of the launch (max over its problems)
+    int lds_limit;                         // device LDS per workgroup (plans depend on it only)
+    int variant;                           // QP_VARIANT_* requested (0 = per-problem plan)
 };
 
 struct BwdLaunch {
@@ -79,10 +78,16 @@ struct BwdLaunch {
     int max_rows;             // largest nz + nineq + neq + 1 of the launch
 };
 
-// Dynamic LDS bytes a problem's vectors need in the forward / backward kernels.
-size_t fwd_vec_lds_bytes(int esz, int n, int m, int p);
+// Forward plan of one problem: which factorization policy its workgroup runs
+// and the dynamic LDS it needs.  Depends only on the problem's own dims, the
+// requested variant and the device LDS limit, so a problem is solved with the
+// same arithmetic alone or inside any batch.
+enum { kPolicyGenericGlobal = 0, kPolicyGenericLds = 1, kPolicyTiledGGlobal = 2, kPolicyTiledGLds = 3,
+       kPolicyNone = -1 };
+int fwd_plan(int esz, int n, int m, int p, int variant, int lds_limit, int *lds_bytes);
+
+// Dynamic LDS bytes a problem's vectors need in the backward kernel.
 size_t bwd_vec_lds_bytes(int esz, int n, int m, int p);
-size_t fwd_h_lds_bytes(int esz, int n);
 
 hipError_t launch_forward(qp_dtype dt, const FwdLaunch &L, hipStream_t st);
 hipError_t launch_backward(qp_dtype dt, const BwdLaunch &L, hipStream_t st);

@@ -1,0 +1,286 @@
+// The primal-dual interior point method of Section 3.1, written once over a
+// factorization policy F that owns the reduced KKT factor (and where G lives).
+//
+// Per iterate (order chosen so that the factor kept for the backward pass is
+// the one of the returned iterate):
+//   residuals r_x, r_s, r_y and mu = s^T lambda / nineq        (KKT conditions)
+//   D = lambda / s, factor [Qs + G^T D G, A^T; A, 0]           (symmetrised K)
+//   stop test
+//   affine direction (eq. cvxgen:affine), step to the boundary, mu_aff,
+//   sigma = (mu_aff / mu)^3, centering-plus-corrector direction
+//   (eq. cvxgen:cc) with the same factor, combined step with 0.99 of the
+//   step to the boundary (capped at 1), update of (z, s, lambda, nu).
+//
+// Policy interface (all calls made by every thread of the workgroup; each
+// call ends with a barrier when its outputs are read by other threads):
+//   bool factor(const T *D)                    form and factor at scaling D
+//   void solve(f, r4, dz, dnu)                 [H A^T; A 0][dz; dnu] = [f; r4]
+//   void gt_mv(v, out)   out = G^T v           void g_mv(x, out)   out = G x
+//   void qs_mv(z, out)   out = Qs z
+//   void finish()                              write the factor to the state
+#pragma once
+#include "qp_core.hpp"
+
+namespace qpmi {
+
+template <typename T>
+struct Prob {
+    int n, m, p;
+    const T *Q, *q, *A, *b, *G, *h;
+    T *z, *lam, *nu, *s;
+    char *state;
+    int out;      // index into status / iters
+    int variant;  // requested variant (QP_VARIANT_*)
+};
+
+template <typename T>
+__device__ __forceinline__ Prob<T> fwd_problem(const FwdLaunch &L, int idx) {
+    Prob<T> P;
+    if (L.desc == nullptr) {
+        const int j = idx;
+        P.n = L.nz; P.m = L.nineq; P.p = L.neq;
+        P.Q = (const T *)L.Q + (size_t)j * L.sQ;
+        P.q = (const T *)L.q + (size_t)j * L.sq;
+        P.A = (const T *)L.A + (size_t)j * L.sA;
+        P.b = (const T *)L.b + (size_t)j * L.sb;
+        P.G = (const T *)L.G + (size_t)j * L.sG;
+        P.h = (const T *)L.h + (size_t)j * L.sh;
+        P.z = (T *)L.z + (size_t)j * P.n;
+        P.lam = (T *)L.lam + (size_t)j * P.m;
+        P.s = (T *)L.s + (size_t)j * P.m;
+        P.nu = (T *)L.nu + (size_t)j * P.p;
+        P.state = L.state + (size_t)j * L.state_stride;
+        P.out = j;
+        P.variant = L.variant;
+    } else {
+        const int j = L.order ? L.order[idx] : idx;
+        const qp_problem_desc d = L.desc[j];
+        const T *base = (const T *)L.base_in;
+        P.n = d.nz; P.m = d.nineq; P.p = d.neq;
+        P.Q = base + d.Q; P.q = base + d.q; P.A = base + d.A;
+        P.b = base + d.b; P.G = base + d.G; P.h = base + d.h;
+        P.z = (T *)L.z + d.z; P.lam = (T *)L.lam + d.lam; P.s = (T *)L.s + d.lam;
+        P.nu = (T *)L.nu + d.nu;
+        P.state = L.state + d.state;
+        P.out = j;
+        P.variant = d.variant ? d.variant : L.variant;
+    }
+    return P;
+}
+
+// LDS vector layout of the interior point driver, in elements of T.  The
+// policy's own LDS region starts at `end`.
+struct IpmLayout {
+    int z, rx, f, y, dza, dzc, tn, tn2;          // n-vectors
+    int s, lam, rz, D, dsa, dla, dsc, dlc, w, tm; // m-vectors
+    int nu, ry, dna, dnc, tp, tp2;               // p-vectors
+    int red;                                     // 64 reduction slots
+    int end;
+    __host__ __device__ IpmLayout(int n, int m, int p) {
+        const int N = pad4(n), M = pad4(m), Pp = pad4(p);
+        int o = 0;
+        z = o; o += N; rx = o; o += N; f = o; o += N; y = o; o += N; dza = o; o += N;
+        dzc = o; o += N; tn = o; o += N; tn2 = o; o += N;
+        s = o; o += M; lam = o; o += M; rz = o; o += M; D = o; o += M; dsa = o; o += M;
+        dla = o; o += M; dsc = o; o += M; dlc = o; o += M; w = o; o += M; tm = o; o += M;
+        nu = o; o += Pp; ry = o; o += Pp; dna = o; o += Pp; dnc = o; o += Pp; tp = o; o += Pp;
+        tp2 = o; o += Pp;
+        red = o; o += 64;
+        end = (o + 15) & ~15;
+    }
+};
+
+template <typename T, int NT, class F>
+__device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayout &Lo, F &fac, int max_iter, T tol,
+                          int32_t *status, int32_t *iters) {
+    const int n = P.n, m = P.m, p = P.p;
+    const int tid = threadIdx.x;
+    T *z = sm + Lo.z, *rx = sm + Lo.rx, *f = sm + Lo.f, *dza = sm + Lo.dza, *dzc = sm + Lo.dzc,
+      *tn = sm + Lo.tn, *tn2 = sm + Lo.tn2;
+    T *s = sm + Lo.s, *lam = sm + Lo.lam, *rz = sm + Lo.rz, *D = sm + Lo.D, *dsa = sm + Lo.dsa,
+      *dla = sm + Lo.dla, *dsc = sm + Lo.dsc, *dlc = sm + Lo.dlc, *w = sm + Lo.w, *tm = sm + Lo.tm;
+    T *nu = sm + Lo.nu, *ry = sm + Lo.ry, *dna = sm + Lo.dna, *dnc = sm + Lo.dnc,
+      *tp = sm + Lo.tp, *tp2 = sm + Lo.tp2;
+    T *red = sm + Lo.red;
+    const T *__restrict__ A = P.A;
+
+    // Input finiteness (one pass over every input).
+    bool fin = true;
+    for (int e = tid; e < n * n; e += NT) fin &= isfinite(P.Q[e]);
+    for (int e = tid; e < m * n; e += NT) fin &= isfinite(P.G[e]);
+    for (int e = tid; e < p * n; e += NT) fin &= isfinite(A[e]);
+    for (int e = tid; e < n; e += NT) fin &= isfinite(P.q[e]);
+    for (int e = tid; e < m; e += NT) fin &= isfinite(P.h[e]);
+    for (int e = tid; e < p; e += NT) fin &= isfinite(P.b[e]);
+    {
+        T bad = fin ? T(0) : T(1), d0 = 0, d1 = 0;
+        block_reduce3<T, NT>(bad, d0, d1, red);
+        fin = bad == T(0);
+    }
+    int st = QP_STATUS_MAX_ITER, it = 0;
+    if (!fin) {
+        st = QP_STATUS_NONFINITE;
+        for (int e = tid; e < n; e += NT) z[e] = 0;
+        for (int e = tid; e < m; e += NT) { s[e] = 0; lam[e] = 0; D[e] = 0; }
+        for (int e = tid; e < p; e += NT) nu[e] = 0;
+        __syncthreads();
+        goto finish;
+    }
+    fac.prepare();
+
+    // ---- initial point: K with the (D(lambda), D(s)) pair replaced by (I, I)
+    for (int e = tid; e < m; e += NT) D[e] = T(1);
+    __syncthreads();
+    {
+        const bool ok = fac.factor(D);
+        if (!ok) {
+            st = QP_STATUS_BREAKDOWN;
+            for (int e = tid; e < n; e += NT) z[e] = 0;
+            for (int e = tid; e < m; e += NT) { s[e] = 0; lam[e] = 0; }
+            for (int e = tid; e < p; e += NT) nu[e] = 0;
+            __syncthreads();
+            goto finish;
+        }
+        // f = -q + G^T h  (r1 = -q, r2 = 0, r3 = h, r4 = b)
+        fac.gt_mv(P.h, f);
+        for (int i = tid; i < n; i += NT) f[i] -= P.q[i];
+        for (int k = tid; k < p; k += NT) tp2[k] = P.b[k];
+        __syncthreads();
+        fac.solve(f, tp2, z, nu);
+        if (m > 0) {
+            fac.g_mv(z, tm);
+            T mns = pinf<T>(), mnl = pinf<T>(), dummy = 0;
+            for (int k = tid; k < m; k += NT) {
+                const T sk = P.h[k] - tm[k];
+                s[k] = sk;
+                lam[k] = -sk;
+                mns = fmin(mns, sk);
+                mnl = fmin(mnl, -sk);
+            }
+            T mx = -pinf<T>();
+            block_reduce3<T, NT>(dummy, mx, mns, red);
+            dummy = 0; mx = -pinf<T>();
+            block_reduce3<T, NT>(dummy, mx, mnl, red);
+            for (int k = tid; k < m; k += NT) {
+                if (mns <= T(0)) s[k] += T(1) - mns;
+                if (mnl <= T(0)) lam[k] += T(1) - mnl;
+            }
+            __syncthreads();
+        } else {
+            st = QP_STATUS_OPTIMAL;
+            goto store_factor;
+        }
+    }
+
+    // ---- Newton loop
+    for (it = 0;; ++it) {
+        // residuals: rx = -(Qs z + q + G^T lam + A^T nu), rz = -(G z + s - h), ry = -(A z - b)
+        fac.qs_mv(z, tn);
+        fac.g_mv(z, tm);
+        fac.gt_mv(lam, rx);
+        if (p > 0) {
+            mv_rows<T, NT>(A, n, p, n, z, ry);  // A z
+            mv_cols<T, NT>(A, n, p, n, nu, tn2);  // A^T nu
+            __syncthreads();
+        }
+        T vsum = 0, vmax = 0, vmin = pinf<T>();
+        for (int i = tid; i < n; i += NT) {
+            T acc = tn[i] + P.q[i] + rx[i];
+            if (p > 0) acc += tn2[i];
+            rx[i] = -acc;
+            vmax = fmax(vmax, fabs(acc));
+            vmin = fmin(vmin, isfinite(acc) ? T(1) : T(0));
+        }
+        for (int k = tid; k < m; k += NT) {
+            const T r = -(tm[k] + s[k] - P.h[k]);
+            rz[k] = r;
+            vmax = fmax(vmax, fabs(r));
+            vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
+            vsum += s[k] * lam[k];
+            D[k] = lam[k] / s[k];
+        }
+        for (int k = tid; k < p; k += NT) {
+            const T r = -(ry[k] - P.b[k]);
+            ry[k] = r;
+            vmax = fmax(vmax, fabs(r));
+            vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
+        }
+        block_reduce3<T, NT>(vsum, vmax, vmin, red);
+        const T mu = vsum / T(m);
+        const T err = fmax(mu, vmax);
+        const bool finite_now = vmin > T(0) && isfinite(mu);
+
+        // factor at this iterate
+        const bool ok = finite_now && fac.factor(D);
+
+        if (!finite_now) { st = QP_STATUS_NONFINITE; break; }
+        if (!ok) { st = QP_STATUS_BREAKDOWN; break; }
+        if (err <= tol) { st = QP_STATUS_OPTIMAL; break; }
+        if (it >= max_iter) { st = QP_STATUS_MAX_ITER; break; }
+
+        // ---- affine direction: f = rx + G^T (lam + D rz), r4 = ry
+        for (int k = tid; k < m; k += NT) tm[k] = lam[k] + D[k] * rz[k];
+        __syncthreads();
+        fac.gt_mv(tm, f);
+        for (int i = tid; i < n; i += NT) f[i] += rx[i];
+        __syncthreads();
+        fac.solve(f, ry, dza, dna);
+        fac.g_mv(dza, tm);
+        T amin = pinf<T>(), d0 = 0, d1 = 0;
+        for (int k = tid; k < m; k += NT) {
+            const T ds = rz[k] - tm[k];
+            const T dl = -lam[k] - D[k] * ds;
+            dsa[k] = ds;
+            dla[k] = dl;
+            if (ds < T(0)) amin = fmin(amin, -s[k] / ds);
+            if (dl < T(0)) amin = fmin(amin, -lam[k] / dl);
+        }
+        block_reduce3<T, NT>(d0, d1, amin, red);
+        const T a_aff = fmin(T(1), amin);
+        T msum = 0;
+        for (int k = tid; k < m; k += NT) msum += (s[k] + a_aff * dsa[k]) * (lam[k] + a_aff * dla[k]);
+        msum = block_sum<T, NT>(msum, red);
+        const T mu_aff = msum / T(m);
+        const T ratio = mu_aff / mu;
+        const T sigma = ratio * ratio * ratio;
+
+        // ---- centering-plus-corrector: w = (sigma mu - dsa dla) / s, f = -G^T w, r4 = 0
+        for (int k = tid; k < m; k += NT) w[k] = (sigma * mu - dsa[k] * dla[k]) / s[k];
+        for (int k = tid; k < p; k += NT) tp[k] = T(0);
+        __syncthreads();
+        fac.gt_mv(w, f);
+        for (int i = tid; i < n; i += NT) f[i] = -f[i];
+        __syncthreads();
+        fac.solve(f, tp, dzc, dnc);
+        fac.g_mv(dzc, tm);
+        amin = pinf<T>(); d0 = 0; d1 = 0;
+        for (int k = tid; k < m; k += NT) {
+            const T dsc_k = -tm[k];
+            const T dlc_k = w[k] - D[k] * dsc_k;
+            const T ds = dsa[k] + dsc_k;
+            const T dl = dla[k] + dlc_k;
+            dsc[k] = ds;
+            dlc[k] = dl;
+            if (ds < T(0)) amin = fmin(amin, -s[k] / ds);
+            if (dl < T(0)) amin = fmin(amin, -lam[k] / dl);
+        }
+        block_reduce3<T, NT>(d0, d1, amin, red);
+        const T alpha = fmin(T(1), T(0.99) * amin);
+        for (int i = tid; i < n; i += NT) z[i] += alpha * (dza[i] + dzc[i]);
+        for (int k = tid; k < m; k += NT) { s[k] += alpha * dsc[k]; lam[k] += alpha * dlc[k]; }
+        for (int k = tid; k < p; k += NT) nu[k] += alpha * (dna[k] + dnc[k]);
+        __syncthreads();
+    }
+
+store_factor:
+    fac.finish(D);
+
+finish:
+    for (int i = tid; i < n; i += NT) P.z[i] = z[i];
+    for (int k = tid; k < m; k += NT) { P.s[k] = s[k]; P.lam[k] = lam[k]; }
+    for (int k = tid; k < p; k += NT) P.nu[k] = nu[k];
+    if (tid == 0) { status[P.out] = st; iters[P.out] = it; }
+    __syncthreads();
+}
+
+}  // namespace qpmi

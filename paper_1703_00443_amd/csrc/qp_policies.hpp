@@ -1,0 +1,496 @@
+// Factorization policies of the interior point driver (qp_ipm.hpp).
+//
+// GenericFactor: the factor lives in LDS (HL) or in the global state buffer;
+//   plain per-element loops; any size; any number of equality rows.
+// TiledFactor: the padded square of 16x16 tiles lives in the registers of
+//   four wavefronts in the MFMA accumulator layout; H = Qs + G^T D G is formed
+//   with v_mfma_*_16x16x4; the Cholesky factorisation and the triangular
+//   inverse are one sequence of rank-1 updates (one barrier per column);
+//   the triangular solves are register matrix-vector products.  nz <= 128,
+//   neq == 0; G is staged in LDS when it fits (GL).
+#pragma once
+#include "qp_ipm.hpp"
+
+namespace qpmi {
+
+__host__ __device__ inline int h_ld(int n) { return n | 1; }
+
+// LDS regions of the policies (elements of T, after the driver's vectors).
+template <bool HL>
+struct GenericLayout {
+    int xd, xdp, y, t1, t2, tq, H, end;
+    __host__ __device__ GenericLayout(int base, int n, int m, int p) {
+        (void)m;
+        int o = base;
+        const int N = pad4(n), Pp = pad4(p);
+        xd = o; o += N; xdp = o; o += Pp; y = o; o += N; t1 = o; o += Pp; t2 = o; o += Pp;
+        tq = o; o += N;
+        o = (o + 15) & ~15;
+        H = o;
+        end = HL ? o + n * h_ld(n) : o;
+    }
+};
+
+template <bool GL>
+struct TiledLayout {
+    int colbuf, part, yv, xv, panel, G, end;
+    __host__ __device__ TiledLayout(int base, int n, int m) {
+        const int nt = (n + 15) / 16, np = 16 * nt;
+        int o = base;
+        colbuf = o; o += 2 * np; part = o; o += nt * np; yv = o; o += np; xv = o; o += np;
+        panel = o; o += np * 17;
+        o = (o + 15) & ~15;
+        G = o;
+        end = GL ? o + m * h_ld(n) : o;
+    }
+};
+
+// ---------------------------------------------------------------------------
+template <typename T, int NT, bool HL>
+struct GenericFactor {
+    int n, m, p;
+    const T *Q, *G, *A;
+    T *H;
+    int ldh;
+    T *U_state, *Dst, *Wt, *US;
+    T *xd, *xdp, *y, *t1, *t2, *tq;
+
+    __device__ GenericFactor(const Prob<T> &P, T *sm, int base) {
+        n = P.n; m = P.m; p = P.p;
+        Q = P.Q; G = P.G; A = P.A;
+        const StateLayout SL = state_layout(sizeof(T), n, m, p);
+        U_state = (T *)(P.state + SL.off_U);
+        Dst = (T *)(P.state + SL.off_D);
+        Wt = (T *)(P.state + SL.off_Wt);
+        US = (T *)(P.state + SL.off_US);
+        const GenericLayout<HL> L(base, n, m, p);
+        xd = sm + L.xd; xdp = sm + L.xdp; y = sm + L.y; t1 = sm + L.t1; t2 = sm + L.t2;
+        tq = sm + L.tq;
+        if (HL) { H = sm + L.H; ldh = h_ld(n); } else { H = U_state; ldh = n; }
+    }
+    __device__ __forceinline__ void prepare() {}
+    __device__ __forceinline__ bool factor(const T *D) {
+        form_h<T, NT>(Q, G, D, n, m, H, ldh);
+        bool ok = chol_inv<T, NT>(H, ldh, n, xd);
+        if (ok && p > 0) ok = schur<T, NT>(H, ldh, A, n, p, Wt, US, xdp);
+        return ok;
+    }
+    __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
+        kkt_solve<T, NT>(H, ldh, Wt, US, n, p, f, r4, y, t1, t2, dz, dnu);
+    }
+    __device__ __forceinline__ void gt_mv(const T *v, T *out) {
+        mv_cols<T, NT>(G, n, m, n, v, out);
+        __syncthreads();
+    }
+    __device__ __forceinline__ void g_mv(const T *x, T *out) {
+        mv_rows<T, NT>(G, n, m, n, x, out);
+        __syncthreads();
+    }
+    __device__ __forceinline__ void qs_mv(const T *z, T *out) {
+        mv_rows<T, NT>(Q, n, n, n, z, tq);
+        mv_cols<T, NT>(Q, n, n, n, z, out);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) out[i] = T(0.5) * (out[i] + tq[i]);
+        __syncthreads();
+    }
+    __device__ __forceinline__ void finish(const T *D) {
+        if (HL)
+            for (int e = threadIdx.x; e < n * n; e += NT) {
+                const int i = e / n, j = e - i * n;
+                U_state[e] = H[(size_t)i * ldh + j];
+            }
+        for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
+        __syncthreads();
+    }
+};
+
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mfma;
+// Operand layouts of v_mfma_*_16x16x4 (lane l = 16 g + c, g = l >> 4, c = l & 15):
+// A[i][k] from lane (k, i), B[k][j] from lane (k, j); the four accumulator
+// values of lane l hold column c and rows row(g, r), r = 0..3.  The row map
+// differs between the f64 (g + 4 r) and the f32 (4 g + r) instructions.
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __host__ __device__ static constexpr int row(int g, int r) { return g + 4 * r; }
+    // 1/sqrt(x), x > 0: hardware estimate refined by two Newton steps (to ~1 ulp)
+    __device__ static __forceinline__ double rsqrt(double x) {
+        double y = __builtin_amdgcn_rsq(x);
+        const double hx = 0.5 * x;
+        y = y * (1.5 - hx * y * y);
+        y = y * (1.5 - hx * y * y);
+        return y;
+    }
+    __device__ static __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __host__ __device__ static constexpr int row(int g, int r) { return 4 * g + r; }
+    __device__ static __forceinline__ float rsqrt(float x) {
+        float y = __builtin_amdgcn_rsqf(x);
+        y = y * (1.5f - 0.5f * x * y * y);
+        return y;
+    }
+    __device__ static __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// The padded square is an 8x8 grid of 16x16 tiles (nz <= 128).  Wavefront w
+// owns tile (s, (w - s) mod 8) in its register slot s: one tile per tile row,
+// spread along anti-diagonals so that the lower triangle is shared evenly.
+constexpr int kTiledWaves = 8;
+
+// The lane id through an opaque move: index arithmetic derived from it is
+// recomputed where it is used instead of being hoisted out of the Newton loop
+// (hoisting it made the tiled kernel spill).
+__device__ __forceinline__ int opaque_tid() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+}
+constexpr int kTiledSlots = 8;
+constexpr int kTiledMaxN = 128;
+
+template <typename T, bool GL>
+struct TiledFactor {
+    static constexpr int NT = 64 * kTiledWaves;
+    using v4 = typename Mfma<T>::v4;
+    int n, m, p, nt, np, ldg;
+    const T *Q, *Gsrc;
+    const T *G;  // LDS copy (GL) or global
+    T *Qs;       // Qs, then the factor, in the state buffer (row-major, ld n)
+    T *Dst;
+    T *colbuf, *part, *yv, *xv, *panel;
+    int w, lane, g, c;
+    v4 sq[kTiledSlots];
+
+    __device__ __forceinline__ int tcol(int s) const { return (w - s) & 7; }
+    __device__ __forceinline__ void lane_ids() {
+        const int t = opaque_tid();
+        lane = t & 63; g = lane >> 4; c = lane & 15;
+        w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: tile skips are scalar branches
+    }
+
+    __device__ TiledFactor(const Prob<T> &P, T *sm, int base) {
+        n = P.n; m = P.m; p = P.p;
+        nt = (n + 15) / 16; np = 16 * nt;
+        Q = P.Q; Gsrc = P.G;
+        const StateLayout SL = state_layout(sizeof(T), n, m, p);
+        Qs = (T *)(P.state + SL.off_U);
+        Dst = (T *)(P.state + SL.off_D);
+        const TiledLayout<GL> L(base, n, m);
+        colbuf = sm + L.colbuf; part = sm + L.part; yv = sm + L.yv; xv = sm + L.xv;
+        panel = sm + L.panel;
+        if (GL) { G = sm + L.G; ldg = h_ld(n); } else { G = Gsrc; ldg = n; }
+        lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
+    }
+
+    __device__ __forceinline__ void prepare() {
+        for (int e = threadIdx.x; e < n * n; e += NT) {
+            const int i = e / n, j = e - i * n;
+            Qs[e] = T(0.5) * (Q[(size_t)i * n + j] + Q[(size_t)j * n + i]);
+        }
+        if (GL)
+            for (int e = threadIdx.x; e < m * n; e += NT) {
+                const int k = e / n, i = e - k * n;
+                const_cast<T *>(G)[(size_t)k * ldg + i] = Gsrc[e];
+            }
+        __syncthreads();
+    }
+
+    // H = Qs + G^T D G into the register tiles (lower tiles), X region zero.
+    __device__ __forceinline__ void form(const T *D) {
+        lane_ids();
+#pragma unroll
+        for (int s = 0; s < kTiledSlots; ++s) {
+            const int I = s, J = tcol(s);
+            if (I >= nt || J >= nt) continue;
+            v4 acc = {0, 0, 0, 0};
+            if (I >= J) {
+                const int ci = 16 * I + c, cj = 16 * J + c;
+                for (int kb = 0; kb < m; kb += 4) {
+                    const int k = kb + g;
+                    T a = 0, b = 0;
+                    if (k < m) {
+                        if (ci < n) a = G[(size_t)k * ldg + ci];
+                        if (cj < n) b = D[k] * G[(size_t)k * ldg + cj];
+                    }
+                    acc = Mfma<T>::mma(a, b, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * I + Mfma<T>::row(g, r), col = cj;
+                    if (row < n && col < n) acc[r] += Qs[(size_t)row * n + col];
+                    else if (row == col) acc[r] = T(1);
+                    if (row < col) acc[r] = T(0);
+                }
+            }
+            sq[s] = acc;
+        }
+    }
+
+    // Publish column kk of the square to colbuf[kk & 1].
+    __device__ __forceinline__ void publish(int kk) {
+        T *buf = colbuf + (kk & 1) * np;
+        const int Jk = kk >> 4, ck = kk & 15;
+#pragma unroll
+        for (int s = 0; s < kTiledSlots; ++s) {
+            const int I = s, J = tcol(s);
+            if (I >= nt || J >= nt) continue;
+            if (J == Jk && c == ck) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) buf[16 * I + Mfma<T>::row(g, r)] = sq[s][r];
+            }
+        }
+    }
+
+    // Fused Cholesky + inverse.  Step k is the rank-1 update
+    //     S[r][c] -= s_r s_c   where r >= c > k (trailing block of L)
+    //                          or    r <= k < c (rows of X = L^{-1})
+    // with s = column k of S scaled by 1/sqrt(S[k][k]) and s_k = 1/sqrt(S[k][k]);
+    // column k is then replaced by s.  After all steps the strict lower triangle
+    // holds L, the diagonal 1/L[k][k] and the strict upper triangle X^T, so the
+    // upper triangle (incl. diagonal) is U = L^{-T}.
+    // Blocked by 16-column panels: the 16 rank-1 steps of a panel update only
+    // the panel's tile column (one tile per wavefront); their effect on the
+    // columns to the right is applied afterwards as one rank-16 MFMA update
+    // per tile, masked where the rank-1 conditions exclude a step.
+    __device__ __forceinline__ bool chol_inv() {
+        lane_ids();
+        publish(0);
+        __syncthreads();
+        for (int P = 0; P < nt; ++P) {
+            // ---- panel: 16 dependent rank-1 steps on tile column P.  Wave w owns
+            // the panel tile of tile row R = (w - P) mod 8; it is copied out of
+            // the slot array once so the steps touch four registers only.
+            lane_ids();
+            const int R = (w - P) & 7;
+            const bool has = R < nt;
+            v4 pt = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < kTiledSlots; ++s)
+                if (s == R) pt = sq[s];
+            int rows[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rows[r] = 16 * R + Mfma<T>::row(g, r);
+            const int col0 = 16 * P + c;
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = 16 * P + kk;
+                const T *buf = colbuf + (k & 1) * np;
+                const T vk = buf[k];
+                if (!(vk > T(0)) || !isfinite(vk)) return false;
+                if (has) {
+                    const T inv = Mfma<T>::rsqrt(vk);
+                    const T wc = buf[col0] * (inv * inv);
+                    const bool upd_c = c > kk, fin_c = c == kk;
+                    if (R != P) {
+                        // off-diagonal panel tile: rows never equal k, every row
+                        // satisfies the row condition (r > c for R > P, r <= k for R < P)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const T v = buf[rows[r]];
+                            const T xu = upd_c ? pt[r] - v * wc : pt[r];
+                            pt[r] = fin_c ? v * inv : xu;
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = rows[r];
+                            const T v = (row == k) ? T(1) : buf[row];
+                            const bool upd = upd_c && (row >= col0 || row <= k);
+                            const T xu = upd ? pt[r] - v * wc : pt[r];
+                            pt[r] = fin_c ? v * inv : xu;
+                        }
+                    }
+                    if (kk < 15 && c == kk + 1) {
+                        T *nb = colbuf + ((k + 1) & 1) * np;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) nb[rows[r]] = pt[r];
+                    }
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int s = 0; s < kTiledSlots; ++s)
+                if (s == R) sq[s] = pt;
+            if (P + 1 == nt) break;
+            // ---- the finished panel (tile column P) to LDS, ld 17
+#pragma unroll
+            for (int s = 0; s < kTiledSlots; ++s) {
+                if (s >= nt || tcol(s) != P) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    panel[(16 * s + Mfma<T>::row(g, r)) * 17 + c] = sq[s][r];
+            }
+            __syncthreads();
+            // ---- rank-16 update of the tiles right of the panel
+            lane_ids();
+#pragma unroll
+            for (int s = 0; s < kTiledSlots; ++s) {
+                const int R = s, C = tcol(s);
+                if (R >= nt || C >= nt || C <= P) continue;
+                if (R > P && R < C) continue;  // rows of X below the panel: no step applies
+                v4 d = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kq = 4 * q + g;
+                    T a = panel[(16 * R + c) * 17 + kq];
+                    if (R == P) a = (kq >= c) ? a : T(0);  // X rows of the panel: steps k >= r only
+                    const T b = panel[(16 * C + c) * 17 + kq];
+                    d = Mfma<T>::mma(a, b, d);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * R + Mfma<T>::row(g, r), col = 16 * C + c;
+                    const bool keep = !(R == C && row < col);  // X part of a diagonal tile: untouched
+                    sq[s][r] -= keep ? d[r] : T(0);
+                }
+            }
+            publish(16 * (P + 1));
+            __syncthreads();
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ bool factor(const T *D) {
+        form(D);
+        return chol_inv();
+    }
+
+    // y = U^T f then dz = U y with U = L^{-T} in the upper register tiles.
+    __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
+        (void)r4; (void)dnu;
+        lane_ids();
+#pragma unroll
+        for (int s = 0; s < kTiledSlots; ++s) {
+            const int I = s, J = tcol(s);
+            if (I >= nt || J >= nt) continue;
+            if (I > J) continue;
+            const int col = 16 * J + c;
+            T acc = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * I + Mfma<T>::row(g, r);
+                const T fr = f[row < n ? row : 0];
+                acc += (row <= col && row < n) ? sq[s][r] * fr : T(0);
+            }
+            acc += __shfl_xor(acc, 16, 64);
+            acc += __shfl_xor(acc, 32, 64);
+            if (g == 0) part[I * np + col] = acc;
+        }
+        __syncthreads();
+        for (int col = threadIdx.x; col < np; col += NT) {
+            T acc = 0;
+            for (int I = 0; I <= (col >> 4); ++I) acc += part[I * np + col];
+            yv[col] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kTiledSlots; ++s) {
+            const int I = s, J = tcol(s);
+            if (I >= nt || J >= nt) continue;
+            if (I > J) continue;
+            const int col = 16 * J + c;
+            const T yc = yv[col];
+            T v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * I + Mfma<T>::row(g, r);
+                v[r] = (col >= row) ? sq[s][r] * yc : T(0);
+            }
+            // reduce-scatter over the 16 lanes of the row group
+            const bool hi = (c & 8) != 0;
+            T k0 = hi ? v[2] : v[0], k1 = hi ? v[3] : v[1];
+            k0 += __shfl_xor(hi ? v[0] : v[2], 8, 64);
+            k1 += __shfl_xor(hi ? v[1] : v[3], 8, 64);
+            const bool h2 = (c & 4) != 0;
+            T keep = h2 ? k1 : k0;
+            keep += __shfl_xor(h2 ? k0 : k1, 4, 64);
+            keep += __shfl_xor(keep, 2, 64);
+            keep += __shfl_xor(keep, 1, 64);
+            if ((c & 3) == 0) part[J * np + 16 * I + Mfma<T>::row(g, (hi ? 2 : 0) + (h2 ? 1 : 0))] = keep;
+        }
+        __syncthreads();
+        for (int row = threadIdx.x; row < n; row += NT) {
+            T acc = 0;
+            for (int J = row >> 4; J < nt; ++J) acc += part[J * np + row];
+            dz[row] = acc;
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void gt_mv(const T *v, T *out) {
+        for (int i = threadIdx.x; i < n; i += NT) {
+            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int k = 0;
+            for (; k + 3 < m; k += 4) {
+                a0 += G[(size_t)k * ldg + i] * v[k];
+                a1 += G[(size_t)(k + 1) * ldg + i] * v[k + 1];
+                a2 += G[(size_t)(k + 2) * ldg + i] * v[k + 2];
+                a3 += G[(size_t)(k + 3) * ldg + i] * v[k + 3];
+            }
+            for (; k < m; ++k) a0 += G[(size_t)k * ldg + i] * v[k];
+            out[i] = (a0 + a1) + (a2 + a3);
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ void g_mv(const T *x, T *out) {
+        if (GL) {
+            for (int k = threadIdx.x; k < m; k += NT) {
+                const T *row = G + (size_t)k * ldg;
+                T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+                int i = 0;
+                for (; i + 3 < n; i += 4) {
+                    a0 += row[i] * x[i];
+                    a1 += row[i + 1] * x[i + 1];
+                    a2 += row[i + 2] * x[i + 2];
+                    a3 += row[i + 3] * x[i + 3];
+                }
+                for (; i < n; ++i) a0 += row[i] * x[i];
+                out[k] = (a0 + a1) + (a2 + a3);
+            }
+        } else {
+            mv_rows<T, NT>(G, ldg, m, n, x, out);
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ void qs_mv(const T *z, T *out) {
+        // Qs is symmetric: column sums over coalesced rows
+        for (int i = threadIdx.x; i < n; i += NT) {
+            T a0 = 0, a1 = 0;
+            int j = 0;
+            for (; j + 1 < n; j += 2) {
+                a0 += Qs[(size_t)j * n + i] * z[j];
+                a1 += Qs[(size_t)(j + 1) * n + i] * z[j + 1];
+            }
+            if (j < n) a0 += Qs[(size_t)j * n + i] * z[j];
+            out[i] = a0 + a1;
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ void finish(const T *D) {
+        lane_ids();
+#pragma unroll
+        for (int s = 0; s < kTiledSlots; ++s) {
+            const int I = s, J = tcol(s);
+            if (I >= nt || J >= nt) continue;
+            if (I > J) continue;
+            const int col = 16 * J + c;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * I + Mfma<T>::row(g, r);
+                if (row <= col && row < n && col < n) Qs[(size_t)row * n + col] = sq[s][r];
+            }
+        }
+        for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
+        __syncthreads();
+    }
+};
+
+}  // namespace qpmi

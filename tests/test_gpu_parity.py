@@ -148,3 +148,18 @@ def test_generic_variant_matches_lds_variant_bitwise():
     o2 = _run(b, np.float64, opts_over={"variant": qb.VARIANT_GENERIC})
     for k in ("z", "lam", "nu", "iters", "dQ", "dG", "dA"):
         np.testing.assert_array_equal(o1[k], o2[k])
+
+
+@pytest.mark.parametrize("variant", ["auto", "generic"])
+@pytest.mark.parametrize("dims", [(1, 3, 0), (15, 20, 0), (16, 16, 0), (17, 40, 0), (100, 100, 0),
+                                  (128, 96, 0), (129, 64, 0)])
+def test_variants_across_tile_edges(variant, dims):
+    """Sizes around the 16-wide tiles and the 128-variable limit of the tiled
+    policy, with the per-problem plan (auto) and with the generic policy."""
+    from paper_1703_00443_amd import binding as qb
+    n, m, p = dims
+    b = synth.make_batch(seed=31337, B=2, n=n, m=m, p=p, row_normalize=True)
+    over = {"variant": qb.VARIANT_GENERIC} if variant == "generic" else None
+    for dtype in (np.float64, np.float32):
+        out = _run(b, dtype, opts_over=over)
+        _check(b, out, dtype, range(2))
