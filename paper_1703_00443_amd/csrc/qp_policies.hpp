@@ -15,6 +15,22 @@ namespace qpmi {
 
 __host__ __device__ inline int h_ld(int n) { return n | 1; }
 
+// The padded square is an 8x8 grid of 16x16 tiles (nz <= 128).  Wavefront w
+// owns tile (s, (w - s) mod 8) in its register slot s: one tile per tile row,
+// spread along anti-diagonals so that the lower triangle is shared evenly.
+constexpr int kTiledWaves = 8;
+
+// The lane id through an opaque move: index arithmetic derived from it is
+// recomputed where it is used instead of being hoisted out of the Newton loop
+// (hoisting it made the tiled kernel spill).
+__device__ __forceinline__ int opaque_tid() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+}
+constexpr int kTiledSlots = 8;
+constexpr int kTiledMaxN = 128;
+
 // LDS regions of the policies (elements of T, after the driver's vectors).
 template <bool HL>
 struct GenericLayout {
@@ -33,15 +49,18 @@ struct GenericLayout {
 
 template <bool GL>
 struct TiledLayout {
-    int colbuf, part, yv, xv, panel, G, end;
+    int colbuf, part, yv, xv, panel, scratch, dbuf, flag, G, end;
     __host__ __device__ TiledLayout(int base, int n, int m) {
         const int nt = (n + 15) / 16, np = 16 * nt;
         int o = base;
         colbuf = o; o += 2 * np; part = o; o += nt * np; yv = o; o += np; xv = o; o += np;
         panel = o; o += np * 17;
+        scratch = o; o += 64 * kTiledWaves;
+        dbuf = o; o += 16;
+        flag = o; o += 4;
         o = (o + 15) & ~15;
         G = o;
-        end = GL ? o + m * h_ld(n) : o;
+        end = GL ? o + ((m + 3) & ~3) * (np + 1) : o;
     }
 };
 
@@ -141,21 +160,7 @@ struct Mfma<float> {
     }
 };
 
-// The padded square is an 8x8 grid of 16x16 tiles (nz <= 128).  Wavefront w
-// owns tile (s, (w - s) mod 8) in its register slot s: one tile per tile row,
-// spread along anti-diagonals so that the lower triangle is shared evenly.
-constexpr int kTiledWaves = 8;
 
-// The lane id through an opaque move: index arithmetic derived from it is
-// recomputed where it is used instead of being hoisted out of the Newton loop
-// (hoisting it made the tiled kernel spill).
-__device__ __forceinline__ int opaque_tid() {
-    int t;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
-    return t;
-}
-constexpr int kTiledSlots = 8;
-constexpr int kTiledMaxN = 128;
 
 template <typename T, bool GL>
 struct TiledFactor {
@@ -166,7 +171,8 @@ struct TiledFactor {
     const T *G;  // LDS copy (GL) or global
     T *Qs;       // Qs, then the factor, in the state buffer (row-major, ld n)
     T *Dst;
-    T *colbuf, *part, *yv, *xv, *panel;
+    T *colbuf, *part, *yv, *xv, *panel, *scratch, *dbuf;
+    int *flag;
     int w, lane, g, c;
     v4 sq[kTiledSlots];
 
@@ -186,8 +192,9 @@ struct TiledFactor {
         Dst = (T *)(P.state + SL.off_D);
         const TiledLayout<GL> L(base, n, m);
         colbuf = sm + L.colbuf; part = sm + L.part; yv = sm + L.yv; xv = sm + L.xv;
-        panel = sm + L.panel;
-        if (GL) { G = sm + L.G; ldg = h_ld(n); } else { G = Gsrc; ldg = n; }
+        panel = sm + L.panel; scratch = sm + L.scratch; dbuf = sm + L.dbuf;
+        flag = reinterpret_cast<int *>(sm + L.flag);
+        if (GL) { G = sm + L.G; ldg = np + 1; } else { G = Gsrc; ldg = n; }
         lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
     }
 
@@ -196,42 +203,76 @@ struct TiledFactor {
             const int i = e / n, j = e - i * n;
             Qs[e] = T(0.5) * (Q[(size_t)i * n + j] + Q[(size_t)j * n + i]);
         }
-        if (GL)
-            for (int e = threadIdx.x; e < m * n; e += NT) {
-                const int k = e / n, i = e - k * n;
-                const_cast<T *>(G)[(size_t)k * ldg + i] = Gsrc[e];
+        if (GL) {
+            // zero-padded to whole MFMA steps: rows to a multiple of 4, columns to 16*nt
+            const int mp = (m + 3) & ~3;
+            for (int e = threadIdx.x; e < mp * ldg; e += NT) {
+                const int k = e / ldg, i = e - k * ldg;
+                const_cast<T *>(G)[e] = (k < m && i < n) ? Gsrc[(size_t)k * n + i] : T(0);
             }
+        }
         __syncthreads();
     }
 
     // H = Qs + G^T D G into the register tiles (lower tiles), X region zero.
+    // Accumulators start from Qs (identity on the padding); the k loop runs
+    // outside the tile loop so that the MFMAs of the tiles of a wavefront are
+    // independent and overlap their operand loads.
     __device__ __forceinline__ void form(const T *D) {
         lane_ids();
 #pragma unroll
         for (int s = 0; s < kTiledSlots; ++s) {
             const int I = s, J = tcol(s);
-            if (I >= nt || J >= nt) continue;
             v4 acc = {0, 0, 0, 0};
-            if (I >= J) {
-                const int ci = 16 * I + c, cj = 16 * J + c;
-                for (int kb = 0; kb < m; kb += 4) {
-                    const int k = kb + g;
-                    T a = 0, b = 0;
-                    if (k < m) {
-                        if (ci < n) a = G[(size_t)k * ldg + ci];
-                        if (cj < n) b = D[k] * G[(size_t)k * ldg + cj];
-                    }
-                    acc = Mfma<T>::mma(a, b, acc);
-                }
+            if (I < nt && J < nt && I >= J) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * I + Mfma<T>::row(g, r), col = cj;
-                    if (row < n && col < n) acc[r] += Qs[(size_t)row * n + col];
-                    else if (row == col) acc[r] = T(1);
-                    if (row < col) acc[r] = T(0);
+                    const int row = 16 * I + Mfma<T>::row(g, r), col = 16 * J + c;
+                    const bool in = row < n && col < n;
+                    const T qv = Qs[in ? (size_t)row * n + col : 0];
+                    acc[r] = in ? qv : (row == col ? T(1) : T(0));
                 }
             }
             sq[s] = acc;
+        }
+        if (GL) {
+            // padded LDS copy of G: straight-line operand loads, no masks
+            for (int kb = 0; kb < m; kb += 4) {
+                const int k = kb + g;
+                const T *Gk = G + (size_t)k * ldg;
+                const T dk = D[k < m ? k : m - 1] * T(k < m ? 1 : 0);
+#pragma unroll
+                for (int s = 0; s < kTiledSlots; ++s) {
+                    const int I = s, J = tcol(s);
+                    if (I >= nt || J >= nt || I < J) continue;
+                    sq[s] = Mfma<T>::mma(Gk[16 * I + c], dk * Gk[16 * J + c], sq[s]);
+                }
+            }
+        } else {
+            for (int kb = 0; kb < m; kb += 4) {
+                const int k = kb + g;
+                const bool vk = k < m;
+                const T *Gk = G + (size_t)(vk ? k : 0) * ldg;
+                const T dk = vk ? D[k] : T(0);
+#pragma unroll
+                for (int s = 0; s < kTiledSlots; ++s) {
+                    const int I = s, J = tcol(s);
+                    if (I >= nt || J >= nt || I < J) continue;
+                    const int ci = 16 * I + c, cj = 16 * J + c;
+                    const T ga = Gk[ci < n ? ci : 0];
+                    const T gb = Gk[cj < n ? cj : 0];
+                    const T a = (vk && ci < n) ? ga : T(0);
+                    const T b = (cj < n) ? dk * gb : T(0);
+                    sq[s] = Mfma<T>::mma(a, b, sq[s]);
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kTiledSlots; ++s) {
+            if (s >= nt || tcol(s) != s) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (Mfma<T>::row(g, r) < c) sq[s][r] = T(0);  // X part of the diagonal tile
         }
     }
 
@@ -257,80 +298,101 @@ struct TiledFactor {
     // column k is then replaced by s.  After all steps the strict lower triangle
     // holds L, the diagonal 1/L[k][k] and the strict upper triangle X^T, so the
     // upper triangle (incl. diagonal) is U = L^{-T}.
-    // Blocked by 16-column panels: the 16 rank-1 steps of a panel update only
-    // the panel's tile column (one tile per wavefront); their effect on the
-    // columns to the right is applied afterwards as one rank-16 MFMA update
-    // per tile, masked where the rank-1 conditions exclude a step.
+    //
+    // Blocked by 16-column panels P:
+    //  (1) the diagonal tile (P,P) runs the 16 steps alone, inside the one
+    //      wavefront that holds it (wave-local LDS exchange, no workgroup
+    //      barrier): lower part -> L_PP, upper part -> X_PP^T;
+    //  (2) every other tile of the panel column becomes  tile * X_PP^T
+    //      (for rows below the diagonal block this is L_RP = H_RP L_PP^{-T},
+    //      for rows above it the block forward substitution X_PR = X_PP A_PR);
+    //  (3) the columns right of the panel get the rank-16 update of the 16
+    //      steps as one MFMA product per tile, masked where a step's condition
+    //      excludes it.
     __device__ __forceinline__ bool chol_inv() {
-        lane_ids();
-        publish(0);
+        if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
         for (int P = 0; P < nt; ++P) {
-            // ---- panel: 16 dependent rank-1 steps on tile column P.  Wave w owns
-            // the panel tile of tile row R = (w - P) mod 8; it is copied out of
-            // the slot array once so the steps touch four registers only.
             lane_ids();
-            const int R = (w - P) & 7;
-            const bool has = R < nt;
-            v4 pt = {0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < kTiledSlots; ++s)
-                if (s == R) pt = sq[s];
-            int rows[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) rows[r] = 16 * R + Mfma<T>::row(g, r);
-            const int col0 = 16 * P + c;
-            for (int kk = 0; kk < 16; ++kk) {
-                const int k = 16 * P + kk;
-                const T *buf = colbuf + (k & 1) * np;
-                const T vk = buf[k];
-                if (!(vk > T(0)) || !isfinite(vk)) return false;
-                if (has) {
-                    const T inv = Mfma<T>::rsqrt(vk);
-                    const T wc = buf[col0] * (inv * inv);
-                    const bool upd_c = c > kk, fin_c = c == kk;
-                    if (R != P) {
-                        // off-diagonal panel tile: rows never equal k, every row
-                        // satisfies the row condition (r > c for R > P, r <= k for R < P)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const T v = buf[rows[r]];
-                            const T xu = upd_c ? pt[r] - v * wc : pt[r];
-                            pt[r] = fin_c ? v * inv : xu;
-                        }
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int row = rows[r];
-                            const T v = (row == k) ? T(1) : buf[row];
-                            const bool upd = upd_c && (row >= col0 || row <= k);
-                            const T xu = upd ? pt[r] - v * wc : pt[r];
-                            pt[r] = fin_c ? v * inv : xu;
-                        }
-                    }
-                    if (kk < 15 && c == kk + 1) {
-                        T *nb = colbuf + ((k + 1) & 1) * np;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) nb[rows[r]] = pt[r];
-                    }
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int s = 0; s < kTiledSlots; ++s)
-                if (s == R) sq[s] = pt;
-            if (P + 1 == nt) break;
-            // ---- the finished panel (tile column P) to LDS, ld 17
+            const int wd = (2 * P) & 7;  // owner of the diagonal tile (P,P), slot P
+            // ---- (1a) old panel tiles (R != P) to LDS, ld 17
 #pragma unroll
             for (int s = 0; s < kTiledSlots; ++s) {
-                if (s >= nt || tcol(s) != P) continue;
+                if (s >= nt || s == P || tcol(s) != P) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    panel[(16 * s + Mfma<T>::row(g, r)) * 17 + c] = sq[s][r];
+                for (int r = 0; r < 4; ++r) panel[(16 * s + Mfma<T>::row(g, r)) * 17 + c] = sq[s][r];
+            }
+            // ---- (1b) the diagonal tile, 16 dependent steps in one wavefront
+            if (w == wd) {
+                v4 t = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < kTiledSlots; ++s)
+                    if (s == P) t = sq[s];
+                int rl[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) rl[r] = Mfma<T>::row(g, r);
+                bool bad = false;
+                for (int kk = 0; kk < 16; ++kk) {
+                    if (c == kk) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) dbuf[rl[r]] = t[r];
+                    }
+                    // The column written by four lanes must have landed before
+                    // the other lanes read it: a wave-local LDS store is not
+                    // ordered before later loads without an explicit wait.
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __builtin_amdgcn_wave_barrier();
+                    const T vk = dbuf[kk];
+                    const T vc = dbuf[c];
+                    T vr[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) vr[r] = dbuf[rl[r]];
+                    bad |= !(vk > T(0)) || !isfinite(vk);
+                    const T inv = Mfma<T>::rsqrt(vk);
+                    const T wc = vc * (inv * inv);
+                    const bool upd_c = c > kk, fin_c = c == kk;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rl[r];
+                        const T v = (row == kk) ? T(1) : vr[r];
+                        const bool upd = upd_c && (row >= c || row <= kk);
+                        const T xu = upd ? t[r] - v * wc : t[r];
+                        t[r] = fin_c ? v * inv : xu;
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __builtin_amdgcn_wave_barrier();
+                }
+                if (bad && c == 0 && g == 0) *flag = 1;
+#pragma unroll
+                for (int s = 0; s < kTiledSlots; ++s)
+                    if (s == P) sq[s] = t;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) panel[(16 * P + rl[r]) * 17 + c] = t[r];
             }
             __syncthreads();
-            // ---- rank-16 update of the tiles right of the panel
+            if (*flag) return false;
+            // ---- (2) panel tiles R != P:  tile <- tile * X_PP^T
             lane_ids();
+#pragma unroll
+            for (int s = 0; s < kTiledSlots; ++s) {
+                if (s >= nt || s == P || tcol(s) != P) continue;
+                v4 d = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kq = 4 * q + g;
+                    const T a = panel[(16 * s + c) * 17 + kq];
+                    // X_PP^T[kq][c] sits in the upper triangle (incl. diagonal) of tile (P,P)
+                    const T bx = panel[(16 * P + kq) * 17 + c];
+                    const T b = (kq <= c) ? bx : T(0);
+                    d = Mfma<T>::mma(a, b, d);
+                }
+                sq[s] = d;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) panel[(16 * s + Mfma<T>::row(g, r)) * 17 + c] = d[r];
+            }
+            __syncthreads();
+            if (P + 1 == nt) break;
+            // ---- (3) rank-16 update of the tiles right of the panel
 #pragma unroll
             for (int s = 0; s < kTiledSlots; ++s) {
                 const int R = s, C = tcol(s);
@@ -352,7 +414,6 @@ struct TiledFactor {
                     sq[s][r] -= keep ? d[r] : T(0);
                 }
             }
-            publish(16 * (P + 1));
             __syncthreads();
         }
         return true;
@@ -425,55 +486,74 @@ struct TiledFactor {
         __syncthreads();
     }
 
-    __device__ __forceinline__ void gt_mv(const T *v, T *out) {
-        for (int i = threadIdx.x; i < n; i += NT) {
+    // out[i] = sum_{k<rows} M[k][i] v[k] for i < cols: the rows are split into
+    // NT / cols groups whose partial sums are added in a fixed order.
+    __device__ __forceinline__ void colsum(const T *M, int ld, int rows, int cols, const T *v, T *out) {
+        const int ng = cols > 0 ? max(1, min(NT / cols, 8)) : 1;
+        const int chunk = (rows + ng - 1) / ng;
+        const int t = threadIdx.x;
+        if (t < ng * cols) {
+            const int q = t / cols, i = t - q * cols;
+            const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
             T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            int k = 0;
-            for (; k + 3 < m; k += 4) {
-                a0 += G[(size_t)k * ldg + i] * v[k];
-                a1 += G[(size_t)(k + 1) * ldg + i] * v[k + 1];
-                a2 += G[(size_t)(k + 2) * ldg + i] * v[k + 2];
-                a3 += G[(size_t)(k + 3) * ldg + i] * v[k + 3];
+            int k = k0;
+            for (; k + 3 < k1; k += 4) {
+                a0 += M[(size_t)k * ld + i] * v[k];
+                a1 += M[(size_t)(k + 1) * ld + i] * v[k + 1];
+                a2 += M[(size_t)(k + 2) * ld + i] * v[k + 2];
+                a3 += M[(size_t)(k + 3) * ld + i] * v[k + 3];
             }
-            for (; k < m; ++k) a0 += G[(size_t)k * ldg + i] * v[k];
-            out[i] = (a0 + a1) + (a2 + a3);
+            for (; k < k1; ++k) a0 += M[(size_t)k * ld + i] * v[k];
+            scratch[q * cols + i] = (a0 + a1) + (a2 + a3);
+        }
+        __syncthreads();
+        for (int i = t; i < cols; i += NT) {
+            T acc = scratch[i];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * cols + i];
+            out[i] = acc;
         }
         __syncthreads();
     }
+    // out[k] = sum_{i<cols} M[k][i] x[i] for k < rows (LDS-resident M, odd ld):
+    // the columns are split into NT / rows groups.
+    __device__ __forceinline__ void rowdot(const T *M, int ld, int rows, int cols, const T *x, T *out) {
+        const int ng = rows > 0 ? max(1, min(NT / rows, 8)) : 1;
+        const int chunk = (cols + ng - 1) / ng;
+        const int t = threadIdx.x;
+        if (t < ng * rows) {
+            const int q = t / rows, k = t - q * rows;
+            const int i0 = q * chunk, i1 = min(cols, i0 + chunk);
+            const T *row = M + (size_t)k * ld;
+            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int i = i0;
+            for (; i + 3 < i1; i += 4) {
+                a0 += row[i] * x[i];
+                a1 += row[i + 1] * x[i + 1];
+                a2 += row[i + 2] * x[i + 2];
+                a3 += row[i + 3] * x[i + 3];
+            }
+            for (; i < i1; ++i) a0 += row[i] * x[i];
+            scratch[q * rows + k] = (a0 + a1) + (a2 + a3);
+        }
+        __syncthreads();
+        for (int k = t; k < rows; k += NT) {
+            T acc = scratch[k];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * rows + k];
+            out[k] = acc;
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ void gt_mv(const T *v, T *out) { colsum(G, ldg, m, n, v, out); }
     __device__ __forceinline__ void g_mv(const T *x, T *out) {
         if (GL) {
-            for (int k = threadIdx.x; k < m; k += NT) {
-                const T *row = G + (size_t)k * ldg;
-                T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-                int i = 0;
-                for (; i + 3 < n; i += 4) {
-                    a0 += row[i] * x[i];
-                    a1 += row[i + 1] * x[i + 1];
-                    a2 += row[i + 2] * x[i + 2];
-                    a3 += row[i + 3] * x[i + 3];
-                }
-                for (; i < n; ++i) a0 += row[i] * x[i];
-                out[k] = (a0 + a1) + (a2 + a3);
-            }
+            rowdot(G, ldg, m, n, x, out);
         } else {
             mv_rows<T, NT>(G, ldg, m, n, x, out);
+            __syncthreads();
         }
-        __syncthreads();
     }
-    __device__ __forceinline__ void qs_mv(const T *z, T *out) {
-        // Qs is symmetric: column sums over coalesced rows
-        for (int i = threadIdx.x; i < n; i += NT) {
-            T a0 = 0, a1 = 0;
-            int j = 0;
-            for (; j + 1 < n; j += 2) {
-                a0 += Qs[(size_t)j * n + i] * z[j];
-                a1 += Qs[(size_t)(j + 1) * n + i] * z[j + 1];
-            }
-            if (j < n) a0 += Qs[(size_t)j * n + i] * z[j];
-            out[i] = a0 + a1;
-        }
-        __syncthreads();
-    }
+    // Qs is symmetric: column sums over coalesced rows of the global copy
+    __device__ __forceinline__ void qs_mv(const T *z, T *out) { colsum(Qs, n, n, n, z, out); }
     __device__ __forceinline__ void finish(const T *D) {
         lane_ids();
 #pragma unroll
