@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QP solves/s fwd+bwd (B=128,n=m=100) vs plain; p50/p99 latency in serving"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X published dense peaks (vector = matrix)
 HBM_GBS = 8000.0
-KERNEL_SOURCES = ("qp_core.hpp", "qp_forward.hip", "qp_tiled.hpp")
+KERNEL_SOURCES = ("qp_core.hpp", "qp_ipm.hpp", "qp_policies.hpp", "qp_forward.hip")
 
 
 def algorithmic_flops(n, m, p, iters):
@@ -67,19 +67,20 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(dtype, launches_bytes):
-    """HBM traffic of the forward kernel from committed rocprofv3 counter
-    summaries, only if they were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "qp_forward_paper_scale_%s_counters.json" % dtype)
+def traffic_from_profiles(dtype):
+    """HBM bytes per forward launch from the committed rocprofv3 counter summary
+    (profiles/qp_forward_paper_scale_<dtype>.md), only if it was taken on the
+    current kernel sources (its source_hash line matches)."""
+    import re
+    path = os.path.join(ROOT, "profiles", "qp_forward_paper_scale_%s.md" % dtype)
     if not os.path.exists(path):
         return None
-    try:
-        d = json.load(open(path))
-    except Exception:
+    text = open(path).read()
+    h = re.search(r"^source_hash: (\w+)", text, re.M)
+    b = re.search(r"^hbm_bytes_per_launch: (\d+)", text, re.M)
+    if not h or not b or h.group(1) != source_hash():
         return None
-    if d.get("source_hash") != source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
+    return int(b.group(1))
 
 
 def cpu_baseline(batch_np, target_cpu_s=12.0):
@@ -117,6 +118,9 @@ def main():
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed region, run 3 device copies of this many MiB "
+                         "(reference kernel for HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every QP is independent and this build runs on a "
@@ -175,7 +179,7 @@ def main():
     achieved = flops / (fwd_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.dtype]
     esz = 8 if args.dtype == "f64" else 4
-    traffic = traffic_from_profiles(args.dtype, None)
+    traffic = traffic_from_profiles(args.dtype)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 4),
@@ -185,14 +189,23 @@ def main():
                                "row-normalised G, fwd+bwd",
                    "batch": B, "nz": n, "nineq": m, "neq": p,
                    "tol": opts.tol, "max_iter": opts.max_iter, "refine_steps": opts.refine_steps},
-        "roofline": {"kernel": "qp_forward_kernel", "bound": "alu", "achieved": round(achieved, 4),
+        "roofline": {"kernel": "qp_forward_kernel", "bound": "mfma", "achieved": round(achieved, 4),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
                      "traffic": traffic,
                      "flops_per_launch": flops, "launch_ms": round(fwd_ms, 4)},
-        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4), "kernel_source_hash": source_hash(),
         "bwd_hbm_gbs": round(B * backward_bytes(n, m, p, esz) / (bwd_ms * 1e-3) / 1e9, 2),
         "iters_mean": float(iters.mean()), "status_counts": np.bincount(status, minlength=4).tolist(),
     }
+
+    if args.calib_copy_mb:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nel * 4
 
     if not args.no_plain:
         # the same library called once per QP with a host sync per call
