@@ -59,7 +59,11 @@ enum {
     QP_STATUS_BREAKDOWN = 2, /* non-positive or non-finite pivot in the factorization of
                                 the returned iterate; the iterate is returned, the
                                 stored factor (and so any backward) is undefined         */
-    QP_STATUS_NONFINITE = 3  /* non-finite input or iterate                              */
+    QP_STATUS_NONFINITE = 3, /* non-finite input or iterate                              */
+    QP_STATUS_STALLED = 4    /* the factorization of the next iterate lost positive
+                                definiteness in working precision before the tolerance was
+                                met; the last iterate whose factorization succeeded is
+                                returned (iters counts its steps) with its factor stored  */
 };
 
 typedef struct {

@@ -42,7 +42,7 @@ def build(force: bool = False) -> str:
     """Compile qp_oracle.c into liboracle.so (gcc, FP64, no FMA contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+        cmd = ["gcc", "-O3", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
                "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)

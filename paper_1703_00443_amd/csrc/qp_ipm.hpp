@@ -74,6 +74,7 @@ struct IpmLayout {
     int z, rx, f, y, dza, dzc, tn, tn2;          // n-vectors
     int s, lam, rz, D, dsa, dla, dsc, dlc, w, tm; // m-vectors
     int nu, ry, dna, dnc, tp, tp2;               // p-vectors
+    int zp, sp, lp, nup;                         // last iterate with a good factor
     int red;                                     // 64 reduction slots
     int end;
     __host__ __device__ IpmLayout(int n, int m, int p) {
@@ -85,6 +86,7 @@ struct IpmLayout {
         dla = o; o += M; dsc = o; o += M; dlc = o; o += M; w = o; o += M; tm = o; o += M;
         nu = o; o += Pp; ry = o; o += Pp; dna = o; o += Pp; dnc = o; o += Pp; tp = o; o += Pp;
         tp2 = o; o += Pp;
+        zp = o; o += N; sp = o; o += M; lp = o; o += M; nup = o; o += Pp;
         red = o; o += 64;
         end = (o + 15) & ~15;
     }
@@ -101,6 +103,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
       *dla = sm + Lo.dla, *dsc = sm + Lo.dsc, *dlc = sm + Lo.dlc, *w = sm + Lo.w, *tm = sm + Lo.tm;
     T *nu = sm + Lo.nu, *ry = sm + Lo.ry, *dna = sm + Lo.dna, *dnc = sm + Lo.dnc,
       *tp = sm + Lo.tp, *tp2 = sm + Lo.tp2;
+    T *zp = sm + Lo.zp, *sp = sm + Lo.sp, *lp = sm + Lo.lp, *nup = sm + Lo.nup;
     T *red = sm + Lo.red;
     const T *__restrict__ A = P.A;
 
@@ -214,9 +217,23 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         const bool ok = finite_now && fac.factor(D);
 
         if (!finite_now) { st = QP_STATUS_NONFINITE; break; }
-        if (!ok) { st = QP_STATUS_BREAKDOWN; break; }
+        if (!ok) {
+            if (it == 0) { st = QP_STATUS_BREAKDOWN; break; }
+            // working precision exhausted: return the previous iterate, whose
+            // factorization succeeded, with that factor stored
+            for (int i = tid; i < n; i += NT) z[i] = zp[i];
+            for (int k = tid; k < m; k += NT) { s[k] = sp[k]; lam[k] = lp[k]; D[k] = lp[k] / sp[k]; }
+            for (int k = tid; k < p; k += NT) nu[k] = nup[k];
+            __syncthreads();
+            --it;
+            st = fac.factor(D) ? QP_STATUS_STALLED : QP_STATUS_BREAKDOWN;
+            break;
+        }
         if (err <= tol) { st = QP_STATUS_OPTIMAL; break; }
         if (it >= max_iter) { st = QP_STATUS_MAX_ITER; break; }
+        for (int i = tid; i < n; i += NT) zp[i] = z[i];
+        for (int k = tid; k < m; k += NT) { sp[k] = s[k]; lp[k] = lam[k]; }
+        for (int k = tid; k < p; k += NT) nup[k] = nu[k];
 
         // ---- affine direction: f = rx + G^T (lam + D rz), r4 = ry
         for (int k = tid; k < m; k += NT) tm[k] = lam[k] + D[k] * rz[k];

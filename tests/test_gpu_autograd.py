@@ -1,0 +1,87 @@
+"""Differentiation through the torch.autograd.Function (Section 3.1.1).
+
+Checked against (i) torch's finite-difference gradcheck on small problems and
+(ii) the FP64 oracle (eq. eq-d-def + eq. grads at the replayed iterate) at the
+differentiation workload (128 QPs, nz=200, nineq=200, neq=50).  The oracle's
+own backward is pinned at that workload by central finite differences on a
+random 1% of entries (tests/test_oracle_fd_workload.py).
+"""
+import numpy as np
+import pytest
+
+from paper_1703_00443_amd import synth
+
+from parity import TOL_G, g_err, grad_scale, oracle_grads, oracle_replay
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def test_gradcheck_small_fp64():
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd.function import qp_layer
+    b = synth.make_batch(seed=5, B=2, n=4, m=6, p=1)
+    T = lambda x: torch.from_numpy(x).to(_dev()).requires_grad_(True)
+    ins = [T(b.Q), T(b.q), T(b.A), T(b.b), T(b.G), T(b.h)]
+    opts = qb.default_opts(torch.float64, tol=1e-11, max_iter=60)
+    f = lambda Q, q, A, bb, G, h: qp_layer(0.5 * (Q + Q.transpose(1, 2)), q, A, bb, G, h, opts)
+    assert torch.autograd.gradcheck(f, ins, eps=1e-6, atol=2e-5, rtol=1e-3, nondet_tol=1e-9)
+
+
+def test_broadcast_parameters_sum_over_batch():
+    """Q, G, A shared by the batch (no batch dim): their gradient is the batch sum
+    of the per-problem gradients."""
+    import torch
+    from paper_1703_00443_amd.function import qp_layer
+    b = synth.make_batch(seed=6, B=3, n=7, m=9, p=2)
+    dev = _dev()
+    Q = torch.from_numpy(b.Q[0]).to(dev).requires_grad_(True)
+    G = torch.from_numpy(b.G[0]).to(dev).requires_grad_(True)
+    A = torch.from_numpy(b.A[0]).to(dev).requires_grad_(True)
+    q = torch.from_numpy(b.q).to(dev).requires_grad_(True)
+    h = torch.from_numpy(b.h).to(dev)
+    bb = torch.from_numpy(b.b).to(dev)
+    z = qp_layer(Q, q, A, bb, G, h)
+    g = torch.from_numpy(b.g).to(dev)
+    (z * g).sum().backward()
+    dQ = np.zeros_like(b.Q[0]); dG = np.zeros_like(b.G[0]); dA = np.zeros_like(b.A[0])
+    zz = z.detach().cpu().numpy()
+    for i in range(3):
+        P = {"Q": b.Q[0], "q": b.q[i], "A": b.A[0], "b": b.b[i], "G": b.G[0], "h": b.h[i]}
+        import oracle
+        r = oracle.solve(P["Q"], P["q"], P["A"], P["b"], P["G"], P["h"], tol=1e-8)
+        go = oracle_grads(P, r, b.g[i], np.float64)
+        dQ += go["dQ"]; dG += go["dG"]; dA += go["dA"]
+        np.testing.assert_allclose(q.grad[i].cpu().numpy(), go["dq"], atol=1e-5)
+    np.testing.assert_allclose(Q.grad.cpu().numpy(), dQ, atol=1e-5)
+    np.testing.assert_allclose(G.grad.cpu().numpy(), dG, atol=1e-5)
+    np.testing.assert_allclose(A.grad.cpu().numpy(), dA, atol=1e-5)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_differentiation_workload_vs_oracle(dtype):
+    """128 QPs (nz=200, nineq=200, neq=50): gradients of one sampled problem
+    against the oracle at the replayed iterate."""
+    import torch
+    from paper_1703_00443_amd.function import qp_layer
+    b = synth.make_batch(**synth.DIFF_SCALE)
+    dev = _dev()
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(dtype))).to(dev).requires_grad_(True)
+    ins = [T(b.Q), T(b.q), T(b.A), T(b.b), T(b.G), T(b.h)]
+    z, lam, nu, status, iters = qp_layer(*ins, full=True)
+    (z * torch.from_numpy(b.g.astype(dtype)).to(dev)).sum().backward()
+    st = status.cpu().numpy()
+    assert np.all((st == 0) | (st == 1) | (st == 4)), np.bincount(st)
+    i = 17
+    P = b.problem(i)
+    r = oracle_replay(P, int(iters[i]), dtype)
+    go = oracle_grads(P, r, P["g"], dtype)
+    scale = grad_scale(go)
+    for k, t in zip(("dQ", "dq", "dA", "db", "dG", "dh"), ins):
+        e = g_err(t.grad[i].detach().cpu().numpy().astype(np.float64), go[k], scale)
+        assert e <= TOL_G[dtype], (k, e)

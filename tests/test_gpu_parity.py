@@ -41,7 +41,7 @@ def _check(batch, out, dtype, idx, need_grad=True):
     for i in idx:
         P = batch.problem(i)
         st = int(out["status"][i])
-        assert st in (0, 1), "problem %d status %d" % (i, st)
+        assert st in (0, 1, 4), "problem %d status %d" % (i, st)
         r = oracle_replay(P, out["iters"][i], dtype)
         ez = z_err(out["z"][i], r["z"])
         assert ez <= TOL_Z[dtype], "problem %d: z err %.3e" % (i, ez)
