@@ -1,0 +1,136 @@
+"""Project-written autotuner: which forward kernel variant each size bucket uses.
+
+A bucket is (dtype, whether the problem has equality rows, nz range).  For each
+bucket the tuner draws a small set of problems from the seeded generator,
+times forward + backward of every candidate variant (tiled MFMA policy where it
+applies, LDS-resident generic, global-memory generic) as one uneven launch and
+keeps the fastest one whose results are all usable.  The table is a JSON file;
+the variant of a problem depends only on its own dims, so results do not depend
+on what else shares a launch.
+
+    python -m paper_1703_00443_amd.autotune --dtype f32 --out paper_1703_00443_amd/autotune_table.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "autotune_table.json")
+
+BUCKETS = [(1, 16), (17, 32), (33, 64), (65, 96), (97, 128), (129, 192), (193, 256), (257, 384),
+           (385, 512), (513, 1024)]
+VARIANT_NAMES = {0: "auto", 1: "generic", 2: "lds", 3: "tiled"}
+
+
+def bucket_of(n: int) -> int:
+    for i, (lo, hi) in enumerate(BUCKETS):
+        if lo <= n <= hi:
+            return i
+    return len(BUCKETS) - 1
+
+
+def _dkey(dtype) -> str:
+    import torch
+    return "f64" if dtype in (torch.float64, "f64", np.float64) else "f32"
+
+
+class AutotuneTable:
+    def __init__(self, data: Optional[Dict] = None):
+        self.data = data or {}
+
+    def variant_for(self, dtype, n: int, m: int, p: int) -> int:
+        d = self.data.get(_dkey(dtype), {}).get("eq" if p > 0 else "noeq", {})
+        return int(d.get(str(bucket_of(n)), 0))
+
+    @classmethod
+    def load(cls, path: str = DEFAULT_TABLE) -> "AutotuneTable":
+        if not os.path.exists(path):
+            return cls()
+        with open(path) as f:
+            return cls(json.load(f))
+
+    def save(self, path: str = DEFAULT_TABLE):
+        with open(path, "w") as f:
+            json.dump(self.data, f, indent=1, sort_keys=True)
+
+
+def candidates(n: int, p: int):
+    c = [1, 2]
+    if p == 0 and n <= 128:
+        c.append(3)
+    return c
+
+
+def tune(dtype="f32", samples: int = 24, seed: int = 7, reps: int = 3, buckets=None,
+         table: Optional[AutotuneTable] = None, log=print) -> AutotuneTable:
+    import torch
+    from . import synth
+    from .varlen import VarlenBatch
+
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    table = table or AutotuneTable()
+    dk = _dkey(tdt)
+    table.data.setdefault(dk, {})
+    rng = np.random.default_rng(seed)
+    for bi in (buckets if buckets is not None else range(len(BUCKETS))):
+        lo, hi = BUCKETS[bi]
+        for eq in ("noeq", "eq"):
+            dims = []
+            for _ in range(samples):
+                n = int(rng.integers(lo, hi + 1))
+                p = 0 if eq == "noeq" else int(rng.integers(1, max(1, n // 4) + 1)) if n > 1 else 0
+                if eq == "eq" and p == 0:
+                    continue
+                dims.append((n, 2 * n, p))
+            if not dims:
+                continue
+            probs = synth.make_varlen(seed * 1000 + bi, dims)
+            g = [pr["g"] for pr in probs]
+            best = None
+            for v in candidates(max(d[0] for d in dims), 0 if eq == "noeq" else 1):
+                vb = VarlenBatch(probs, dtype=tdt, variants=[v] * len(probs))
+                dl = vb.pack_vectors(g)
+                vb.forward(); vb.backward(dl)
+                torch.cuda.synchronize()
+                st = vb.status[:vb.count].cpu().numpy()
+                if not np.all((st == 0) | (st == 1) | (st == 4)):
+                    log("bucket %s %s variant %s: bad status %s" % (BUCKETS[bi], eq, VARIANT_NAMES[v],
+                                                                   np.bincount(st)))
+                    continue
+                ts = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    vb.forward(); vb.backward(dl)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                t = float(np.median(ts))
+                log("bucket %-10s %-4s variant %-7s %8.3f ms" % (BUCKETS[bi], eq, VARIANT_NAMES[v], t * 1e3))
+                if best is None or t < best[1]:
+                    best = (v, t)
+            if best is not None:
+                table.data[dk].setdefault(eq, {})[str(bi)] = best[0]
+    return table
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dtype", choices=("f32", "f64"), default="f32")
+    ap.add_argument("--samples", type=int, default=24)
+    ap.add_argument("--max-bucket", type=int, default=len(BUCKETS) - 1)
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    args = ap.parse_args()
+    table = AutotuneTable.load(args.out)
+    table = tune(args.dtype, samples=args.samples, buckets=range(args.max_bucket + 1), table=table)
+    table.save(args.out)
+    print(json.dumps(table.data))
+
+
+if __name__ == "__main__":
+    main()

@@ -25,7 +25,7 @@ static int device_lds_limit() {
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             v > 0)
-            cached = std::min(v, kLdsLimit);
+            cached = std::min(v, kLdsLimit) - 64;  // the forward kernel's static LDS
         else
             cached = 64 * 1024;
     }
@@ -201,7 +201,7 @@ int32_t qp_varlen_workspace_query(qp_dtype dtype, int32_t count, const qp_proble
         b = std::max(b, adj_stride_elems(dh[i].nz, dh[i].nineq, dh[i].neq));
         st += state_layout(esz, dh[i].nz, dh[i].nineq, dh[i].neq).bytes;
     }
-    if (fwd) *fwd = 0;
+    if (fwd) *fwd = kAlignBytes;  // work-queue counter
     if (bwd) *bwd = (size_t)count * b * esz;
     if (state_total) *state_total = st;
     return QP_OK;
@@ -212,7 +212,6 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
                           const void *base_in, const qp_opts *opts, void *z, void *lam, void *nu,
                           void *s, void *state, int32_t *status, int32_t *iters, void *ws,
                           size_t ws_bytes, void *stream) {
-    (void)ws; (void)ws_bytes;
     if (!dtype_ok(dtype)) return QP_EDTYPE;
     if (count < 0) return QP_EARG;
     int32_t rc = check_opts(opts);
@@ -220,6 +219,7 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
     if (count == 0) return QP_OK;
     if (!desc_dev || !desc_host || !base_in || !z || !lam || !nu || !s || !state || !status || !iters)
         return QP_EARG;
+    if (!ws || ws_bytes < (size_t)kAlignBytes) return QP_EWS;
     const int esz = esize(dtype);
     const int lim = device_lds_limit();
     int lds = 0;
@@ -245,6 +245,8 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
     L.lds_bytes = lds;
     L.lds_limit = lim;
     L.variant = opts->variant;
+    L.queue = (int *)ws;
+    L.grid = std::min(count, fwd_resident_workgroups(dtype, lds));
     return hip_ret(launch_forward(dtype, L, (hipStream_t)stream));
 }
 

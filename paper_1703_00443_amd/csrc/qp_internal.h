@@ -53,6 +53,8 @@ struct FwdLaunch {
     int lds_bytes;                         // dynamic LDS of the launch (max over its problems)
     int lds_limit;                         // device LDS per workgroup (plans depend on it only)
     int variant;                           // QP_VARIANT_* requested (0 = per-problem plan)
+    int *queue;                            // varlen: work counter (zeroed by the launch), else null
+    int grid;                              // workgroups launched (0 = one per problem)
 };
 
 struct BwdLaunch {
@@ -85,6 +87,9 @@ struct BwdLaunch {
 enum { kPolicyGenericGlobal = 0, kPolicyGenericLds = 1, kPolicyTiledGGlobal = 2, kPolicyTiledGLds = 3,
        kPolicyNone = -1 };
 int fwd_plan(int esz, int n, int m, int p, int variant, int lds_limit, int *lds_bytes);
+
+// Workgroups of the forward kernel that fit on the device at once with this LDS.
+int fwd_resident_workgroups(qp_dtype dt, int lds_bytes);
 
 // Dynamic LDS bytes a problem's vectors need in the backward kernel.
 size_t bwd_vec_lds_bytes(int esz, int n, int m, int p);

@@ -1,0 +1,174 @@
+"""Uneven batches: many QPs of different sizes in one persistent launch.
+
+    vb = VarlenBatch(problems, dtype=torch.float32)   # list of dicts Q,q,[A,b],[G,h]
+    vb.forward()            # qp_forward_varlen: one launch over every problem
+    vb.backward(dl_dz)      # qp_backward_varlen: gradients of the problems in `need`
+    vb.result(i)            # per-problem views (z, lam, nu, s, status, iters, grads)
+
+The packer lays all inputs out in one device buffer, builds the descriptor
+table (qp_problem_desc per problem: dims, element offsets, state byte offset,
+kernel variant) and a launch order with the most expensive problems first, so
+that the kernel's work queue balances the launch.  Per-problem kernel variants
+come from an autotune table keyed only by the problem's own size bucket, so a
+problem is solved with the same arithmetic alone or inside any batch.
+
+Argument marshalling only; the arithmetic runs in libqpmi.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as qb
+
+KEYS = ("Q", "q", "A", "b", "G", "h")
+
+
+def cost_estimate(n: int, m: int, p: int) -> float:
+    """Flops of one factorization (the dominant term of a Newton step)."""
+    return n * (n + 1) * m + n ** 3 / 3.0 + n * n * p + p ** 3 / 3.0
+
+
+class VarlenBatch:
+    def __init__(self, problems: Sequence[Dict], dtype: torch.dtype = torch.float32,
+                 device: Optional[torch.device] = None, variants: Optional[Sequence[int]] = None,
+                 table=None):
+        dev = device or torch.device("cuda:0")
+        self.dtype, self.device = dtype, dev
+        self.count = len(problems)
+        esz = 8 if dtype == torch.float64 else 4
+        descs = (qb.qp_problem_desc * max(1, self.count))()
+        self.dims = []
+        off_in = 0
+        off_z = off_l = off_n = 0
+        off_state = 0
+        chunks = []
+        for i, P in enumerate(problems):
+            Q = np.asarray(P["Q"])
+            n = Q.shape[0]
+            G = P.get("G")
+            A = P.get("A")
+            m = 0 if G is None else int(np.asarray(G).reshape(-1, n).shape[0])
+            p = 0 if A is None else int(np.asarray(A).reshape(-1, n).shape[0])
+            d = descs[i]
+            d.nz, d.nineq, d.neq = n, m, p
+            if variants is not None:
+                d.variant = int(variants[i])
+            elif table is not None:
+                d.variant = int(table.variant_for(dtype, n, m, p))
+            else:
+                d.variant = 0
+            for key, shape in (("Q", (n, n)), ("q", (n,)), ("A", (p, n)), ("b", (p,)),
+                               ("G", (m, n)), ("h", (m,))):
+                setattr(d, key, off_in)
+                v = P.get(key)
+                arr = np.zeros(shape) if v is None else np.asarray(v, dtype=np.float64).reshape(shape)
+                chunks.append(arr.reshape(-1))
+                off_in += int(np.prod(shape))
+            d.z, d.lam, d.nu = off_z, off_l, off_n
+            off_z += n; off_l += m; off_n += p
+            d.state = off_state
+            off_state += qb.state_bytes(dtype, n, m, p)
+            self.dims.append((n, m, p))
+        npdt = np.float64 if dtype == torch.float64 else np.float32
+        host = np.concatenate(chunks).astype(npdt) if chunks else np.zeros(1, npdt)
+        self.base_in = torch.from_numpy(host).to(dev)
+        self.descs_host = descs
+        raw = bytes(memoryview(descs))[: ctypes.sizeof(qb.qp_problem_desc) * self.count]
+        self.descs_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev) if raw else \
+            torch.zeros(1, dtype=torch.uint8, device=dev)
+        order = sorted(range(self.count), key=lambda i: -cost_estimate(*self.dims[i]))
+        self.order = torch.tensor(order, dtype=torch.int32, device=dev)
+        self.z = torch.zeros(max(1, off_z), dtype=dtype, device=dev)
+        self.lam = torch.zeros(max(1, off_l), dtype=dtype, device=dev)
+        self.s = torch.zeros(max(1, off_l), dtype=dtype, device=dev)
+        self.nu = torch.zeros(max(1, off_n), dtype=dtype, device=dev)
+        self.state = torch.zeros(max(1, off_state), dtype=torch.uint8, device=dev)
+        self.status = torch.zeros(max(1, self.count), dtype=torch.int32, device=dev)
+        self.iters = torch.zeros(max(1, self.count), dtype=torch.int32, device=dev)
+        self.grad = torch.zeros_like(self.base_in)
+        fws, bws, _ = self.workspace_bytes()
+        self.fws = torch.zeros(max(1, fws), dtype=torch.uint8, device=dev)
+        self.bws = torch.zeros(max(1, bws), dtype=torch.uint8, device=dev)
+        self._fws_bytes, self._bws_bytes = fws, bws
+        self.offsets = [(descs[i].Q, descs[i].z, descs[i].lam, descs[i].nu) for i in range(self.count)]
+
+    def workspace_bytes(self, opts=None):
+        o = opts if opts is not None else qb.default_opts(self.dtype)
+        f, b, s = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+        qb._check(qb.load_library().qp_varlen_workspace_query(
+            qb.dtype_code(self.dtype), self.count, ctypes.addressof(self.descs_host),
+            ctypes.byref(o), ctypes.byref(f), ctypes.byref(b), ctypes.byref(s)),
+            "qp_varlen_workspace_query")
+        return int(f.value), int(b.value), int(s.value)
+
+    def forward(self, opts=None):
+        o = opts if opts is not None else qb.default_opts(self.dtype)
+        P = qb._ptr
+        rc = qb.load_library().qp_forward_varlen(
+            qb.dtype_code(self.dtype), self.count, P(self.descs_dev), ctypes.addressof(self.descs_host),
+            P(self.order), P(self.base_in), ctypes.byref(o), P(self.z), P(self.lam), P(self.nu), P(self.s),
+            P(self.state), P(self.status), P(self.iters), P(self.fws), self._fws_bytes, qb._stream())
+        qb._check(rc, "qp_forward_varlen")
+        return self
+
+    def backward(self, dl_dz: torch.Tensor, need: Optional[torch.Tensor] = None, opts=None):
+        """dl_dz packed like z (concatenation of the problems' z); `need` an int32
+        mask per problem (None = all).  Gradients land in self.grad, packed like
+        the inputs."""
+        o = opts if opts is not None else qb.default_opts(self.dtype)
+        P = qb._ptr
+        g = dl_dz.to(device=self.device, dtype=self.dtype).contiguous()
+        self._dl = g
+        self._need = None if need is None else need.to(device=self.device, dtype=torch.int32).contiguous()
+        rc = qb.load_library().qp_backward_varlen(
+            qb.dtype_code(self.dtype), self.count, P(self.descs_dev), ctypes.addressof(self.descs_host),
+            P(self._need), P(self.base_in), ctypes.byref(o), P(self.z), P(self.lam), P(self.nu), P(self.s),
+            P(self.state), P(g), P(self.grad), P(self.bws), self._bws_bytes, qb._stream())
+        qb._check(rc, "qp_backward_varlen")
+        return self
+
+    # ---- unpacking --------------------------------------------------------------------------
+    def views(self, i: int) -> Dict[str, torch.Tensor]:
+        n, m, p = self.dims[i]
+        oin, oz, ol, on = self.offsets[i]
+        d = self.descs_host[i]
+        g = self.grad
+        return {
+            "z": self.z[oz:oz + n], "lam": self.lam[ol:ol + m], "s": self.s[ol:ol + m],
+            "nu": self.nu[on:on + p], "status": self.status[i], "iters": self.iters[i],
+            "dQ": g[d.Q:d.Q + n * n].view(n, n), "dq": g[d.q:d.q + n],
+            "dA": g[d.A:d.A + p * n].view(p, n), "db": g[d.b:d.b + p],
+            "dG": g[d.G:d.G + m * n].view(m, n), "dh": g[d.h:d.h + m],
+        }
+
+    def result(self, i: int) -> Dict[str, np.ndarray]:
+        return {k: (v.cpu().numpy() if v.dim() else int(v.item())) for k, v in self.views(i).items()}
+
+    def pack_vectors(self, vecs: List[np.ndarray]) -> torch.Tensor:
+        """Concatenate per-problem z-shaped vectors (e.g. dl/dz) in packing order."""
+        npdt = np.float64 if self.dtype == torch.float64 else np.float32
+        return torch.from_numpy(np.concatenate([np.asarray(v, dtype=npdt) for v in vecs])).to(self.device)
+
+
+def capture_graph(vb: VarlenBatch, dl_dz: torch.Tensor, need: Optional[torch.Tensor] = None,
+                  opts=None):
+    """Capture forward + backward of an uneven batch into a HIP graph (torch.cuda.CUDAGraph).
+    The launches read the batch's device buffers, so refreshing the inputs in place
+    (vb.base_in, the dl_dz tensor) and replaying the graph re-solves.  The graph
+    holds kernel nodes only (the work-queue counter is cleared by a kernel)."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        vb.forward(opts)
+        vb.backward(dl_dz, need, opts)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        vb.forward(opts)
+        vb.backward(dl_dz, need, opts)
+    return g
