@@ -110,6 +110,83 @@ def cpu_baseline(batch_np, target_cpu_s=12.0):
                       "one QP per thread" % (count, min(count, B) - 1)}
 
 
+def bench_uneven(args):
+    """4096 QPs (default), nz ~ U{8..256}, nineq = 2 nz, neq ~ U{0..nz/4}, FP32, one
+    persistent launch per pass (forward + backward), HIP-graph captured."""
+    import torch
+    from paper_1703_00443_amd import synth
+    from paper_1703_00443_amd.autotune import AutotuneTable
+    from paper_1703_00443_amd.varlen import VarlenBatch, capture_graph
+    count = args.count or 4096
+    dims = synth.varlen_dims(4096, count)
+    probs = synth.make_varlen(4096, dims, dtype=np.float32)
+    vb = VarlenBatch(probs, dtype=torch.float32, table=AutotuneTable.load())
+    dl = vb.pack_vectors([p["g"] for p in probs])
+    g = capture_graph(vb, dl)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    st = vb.status[:count].cpu().numpy()
+    it = vb.iters[:count].cpu().numpy()
+    flops = sum(algorithmic_flops(n, m, p, [k]) for (n, m, p), k in zip(dims, it))
+    return {"metric": "uneven batch QP solves/s fwd+bwd", "value": round(count / el, 2),
+            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(el * 1e3, 3), "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "%d QPs, nz~U{8..256}, nineq=2nz, "
+                                            "neq~U{0..nz/4}, one persistent launch, graph-captured"
+                                            % count},
+            "fwd_algorithmic_tflops": round(flops / el / 1e12, 3),
+            "status_counts": np.bincount(st, minlength=5).tolist(), "iters_mean": float(it.mean())}
+
+
+def bench_serving(args):
+    """Poisson request stream (n log-uniform in [16, 512], nineq ~ U{n..2n},
+    neq ~ U{0..n/8}, half with a backward, FP32) through the continuous-batching
+    server at 25/50/80% of the saturated rate; p50/p99 latency per rate."""
+    import torch
+    from paper_1703_00443_amd import synth
+    from paper_1703_00443_amd.serve import Server, percentiles
+    count = args.count or 400
+    dims = synth.serving_dims(4, count)
+    probs = synth.make_varlen(4, [d[:3] for d in dims], dtype=np.float32)
+
+    def run(rate):
+        srv = Server(dtype=torch.float32, hbm_budget=4 << 30, max_inflight=4)
+        rng = np.random.default_rng(11)
+        futs = []
+        t0 = time.perf_counter()
+        for P, d in zip(probs, dims):
+            futs.append(srv.submit(P, need_backward=d[3], dl_dz=P["g"] if d[3] else None))
+            if rate:
+                time.sleep(rng.exponential(1.0 / rate))
+        lat = [f.result(timeout=600)["latency"] for f in futs]
+        el = time.perf_counter() - t0
+        srv.close()
+        return count / el, lat, srv.stats
+
+    run(0)  # warm-up: code objects, allocator, pinned buffers
+    sat, lat0, _ = run(0)
+    out = {"metric": "serving: QP requests/s and p50/p99 latency", "value": round(sat, 2),
+           "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": "%d requests, n log-uniform [16,512], "
+                                           "nineq~U{n..2n}, neq~U{0..n/8}, 50%% backward" % count},
+           "saturated": {"requests_per_s": round(sat, 2), **{k: round(v * 1e3, 3) for k, v in
+                                                            percentiles(lat0).items()}},
+           "rates": []}
+    for frac in (0.25, 0.5, 0.8):
+        thr, lat, stats = run(frac * sat)
+        out["rates"].append({"offered_per_s": round(frac * sat, 2), "achieved_per_s": round(thr, 2),
+                             **{k + "_ms": round(v * 1e3, 3) for k, v in percentiles(lat).items()},
+                             "launches": stats["launches"],
+                             "max_concurrent_launches": stats["max_concurrent_launches"]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +195,10 @@ def main():
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--workload", choices=("paper", "uneven", "serving"), default="paper",
+                    help="paper: the headline metric (default); uneven: 4096 QPs of mixed sizes in "
+                         "one persistent launch; serving: Poisson request stream, p50/p99 latency")
+    ap.add_argument("--count", type=int, default=0, help="problems/requests for uneven/serving")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, run 3 device copies of this many MiB "
                          "(reference kernel for HBM counter calibration under rocprofv3)")
@@ -135,6 +216,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
+    if args.workload == "uneven":
+        print(json.dumps(bench_uneven(args)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
     dev = torch.device("cuda:0")
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     npdt = np.float64 if args.dtype == "f64" else np.float32

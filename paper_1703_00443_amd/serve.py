@@ -1,0 +1,252 @@
+"""Serving loop with continuous batching for QP layer requests.
+
+    srv = Server(dtype=torch.float32, hbm_budget=4 << 30, max_inflight=4)
+    fut = srv.submit({"Q":..., "q":..., "G":..., "h":..., "A":..., "b":...},
+                     need_backward=True, dl_dz=g)
+    res = fut.result()        # dict: z, lam, nu, s, status, iters, grads (if asked), latency
+    srv.close()
+
+Requests arrive at any time.  A scheduler thread admits waiting requests
+whenever an in-flight slot (one HIP stream per slot, default priority) is free
+and the HBM footprint of everything in flight stays within the budget; the
+admitted requests go out as one uneven-batch launch (forward, then backward for
+the requests that asked for one) while earlier launches are still running on
+other streams, so their work overlaps on the device.  A request larger than the
+whole budget is rejected at submission.  Each launch records an event; the
+scheduler completes the futures of a launch when its event has fired.
+
+The device work sits behind a small backend interface (`launch`, `ready`,
+`collect`) so that the scheduler can be exercised without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import queue
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+class RejectedError(RuntimeError):
+    """The request's HBM footprint exceeds the server's whole budget."""
+
+
+@dataclass
+class Request:
+    problem: Dict
+    need_backward: bool
+    dl_dz: Optional[np.ndarray]
+    footprint: int
+    t_arrival: float
+    future: Future = field(default_factory=Future)
+    dims: tuple = ()
+
+
+def footprint_bytes(n: int, m: int, p: int, esz: int, need_backward: bool) -> int:
+    """Device bytes one request occupies while in flight: packed inputs, outputs,
+    factor state, and for a backward the gradients and adjoint workspace."""
+    inputs = n * n + n + p * n + p + m * n + m
+    outputs = n + 2 * m + p
+    state = n * n + m + p * n + p * p + 4 * 64
+    total = inputs + outputs + state
+    if need_backward:
+        total += inputs + n + (n + m + p + 64)
+    return int(total * esz + 4096)
+
+
+class DeviceBackend:
+    """Launches admitted requests on HIP streams through VarlenBatch."""
+
+    def __init__(self, dtype, device=None, table=None, opts=None):
+        import torch
+        from .autotune import AutotuneTable
+        self.torch = torch
+        self.dtype = dtype
+        self.device = device or torch.device("cuda:0")
+        self.table = table if table is not None else AutotuneTable.load()
+        self.opts = opts
+        self.esz = 8 if dtype == torch.float64 else 4
+
+    def new_slot(self):
+        return self.torch.cuda.Stream(device=self.device)
+
+    def launch(self, slot, reqs: List[Request]):
+        torch = self.torch
+        from .varlen import VarlenBatch
+        torch.cuda.set_device(self.device)
+        with torch.cuda.stream(slot):
+            vb = VarlenBatch([r.problem for r in reqs], dtype=self.dtype, device=self.device,
+                             table=self.table)
+            vb.forward(self.opts)
+            nb = [r.need_backward for r in reqs]
+            if any(nb):
+                dl = vb.pack_vectors([r.dl_dz if r.need_backward else np.zeros(r.dims[0]) for r in reqs])
+                need = torch.tensor([1 if b else 0 for b in nb], dtype=torch.int32)
+                vb.backward(dl, need=need, opts=self.opts)
+            # results go to pinned host buffers asynchronously on the same stream
+            host = {}
+            for k in ("z", "lam", "nu", "s", "status", "iters") + (("grad",) if any(nb) else ()):
+                src = getattr(vb, k)
+                dst = torch.empty(src.shape, dtype=src.dtype, pin_memory=True)
+                dst.copy_(src, non_blocking=True)
+                host[k] = dst
+            host.setdefault("grad", None)
+            ev = torch.cuda.Event()
+            ev.record(slot)
+        return {"vb": vb, "host": host, "event": ev}
+
+    def ready(self, handle) -> bool:
+        return handle["event"].query()
+
+    def collect(self, handle, reqs: List[Request]) -> List[Dict]:
+        vb, host = handle["vb"], handle["host"]
+        out = []
+        for i, r in enumerate(reqs):
+            n, m, p = vb.dims[i]
+            _, oz, ol, on = vb.offsets[i]
+            d = vb.descs_host[i]
+            res = {"z": host["z"][oz:oz + n].numpy(), "lam": host["lam"][ol:ol + m].numpy(),
+                   "s": host["s"][ol:ol + m].numpy(), "nu": host["nu"][on:on + p].numpy(),
+                   "status": int(host["status"][i]), "iters": int(host["iters"][i])}
+            if r.need_backward:
+                g = host["grad"]
+                res.update({"dQ": g[d.Q:d.Q + n * n].view(n, n).numpy(), "dq": g[d.q:d.q + n].numpy(),
+                            "dA": g[d.A:d.A + p * n].view(p, n).numpy(), "db": g[d.b:d.b + p].numpy(),
+                            "dG": g[d.G:d.G + m * n].view(m, n).numpy(), "dh": g[d.h:d.h + m].numpy()})
+            out.append(res)
+        return out
+
+
+class Server:
+    def __init__(self, backend=None, dtype=None, hbm_budget: int = 4 << 30, max_inflight: int = 4,
+                 max_batch: int = 512, idle_sleep: float = 2e-4):
+        if backend is None:
+            import torch
+            backend = DeviceBackend(dtype if dtype is not None else torch.float32)
+        self.backend = backend
+        self.esz = getattr(backend, "esz", 4)
+        self.budget = int(hbm_budget)
+        self.max_batch = max_batch
+        self.idle_sleep = idle_sleep
+        self.slots = [backend.new_slot() for _ in range(max_inflight)]
+        self.free_slots = collections.deque(range(max_inflight))
+        self.waiting: "collections.deque[Request]" = collections.deque()
+        self.incoming: "queue.Queue[Request]" = queue.Queue()
+        self.inflight: List = []  # (slot index, handle, requests, bytes)
+        self.bytes_in_flight = 0
+        self.stats = {"admitted": 0, "rejected": 0, "launches": 0, "max_bytes_in_flight": 0,
+                      "max_concurrent_launches": 0, "max_queue": 0}
+        self._stop = threading.Event()
+        self._lock = threading.Lock()
+        self._thread = threading.Thread(target=self._loop, name="qp-server", daemon=True)
+        self._thread.start()
+
+    # ---- client side ---------------------------------------------------------------------
+    def submit(self, problem: Dict, need_backward: bool = False, dl_dz=None) -> Future:
+        Q = np.asarray(problem["Q"])
+        n = Q.shape[0]
+        m = 0 if problem.get("G") is None else int(np.asarray(problem["G"]).reshape(-1, n).shape[0])
+        p = 0 if problem.get("A") is None else int(np.asarray(problem["A"]).reshape(-1, n).shape[0])
+        fp = footprint_bytes(n, m, p, self.esz, need_backward)
+        req = Request(problem, need_backward, None if dl_dz is None else np.asarray(dl_dz), fp,
+                      time.perf_counter(), dims=(n, m, p))
+        if need_backward and req.dl_dz is None:
+            req.future.set_exception(ValueError("need_backward requires dl_dz"))
+            return req.future
+        if fp > self.budget:
+            with self._lock:
+                self.stats["rejected"] += 1
+            req.future.set_exception(RejectedError(
+                "request needs %d bytes of HBM, the server budget is %d" % (fp, self.budget)))
+            return req.future
+        self.incoming.put(req)
+        return req.future
+
+    def close(self, timeout: float = 60.0):
+        self._stop.set()
+        self._thread.join(timeout)
+
+    # ---- scheduler -----------------------------------------------------------------------
+    def _drain_incoming(self):
+        while True:
+            try:
+                self.waiting.append(self.incoming.get_nowait())
+            except queue.Empty:
+                break
+        self.stats["max_queue"] = max(self.stats["max_queue"], len(self.waiting))
+
+    def _complete(self):
+        still = []
+        for slot, handle, reqs, nbytes in self.inflight:
+            if self.backend.ready(handle):
+                try:
+                    results = self.backend.collect(handle, reqs)
+                    now = time.perf_counter()
+                    for r, res in zip(reqs, results):
+                        res["latency"] = now - r.t_arrival
+                        if not r.future.cancelled():
+                            r.future.set_result(res)
+                except Exception as e:  # surface device errors on every request of the launch
+                    for r in reqs:
+                        if not r.future.done():
+                            r.future.set_exception(e)
+                self.bytes_in_flight -= nbytes
+                self.free_slots.append(slot)
+            else:
+                still.append((slot, handle, reqs, nbytes))
+        self.inflight = still
+
+    def _admit_and_launch(self) -> bool:
+        if not self.waiting or not self.free_slots:
+            return False
+        batch, nbytes = [], 0
+        kept = collections.deque()
+        while self.waiting and len(batch) < self.max_batch:
+            r = self.waiting.popleft()
+            if r.future.cancelled():
+                continue
+            if self.bytes_in_flight + nbytes + r.footprint <= self.budget:
+                batch.append(r)
+                nbytes += r.footprint
+            else:
+                kept.append(r)  # waits until memory frees up
+        kept.extend(self.waiting)
+        self.waiting = kept
+        if not batch:
+            return False
+        slot = self.free_slots.popleft()
+        try:
+            handle = self.backend.launch(self.slots[slot], batch)
+        except Exception as e:
+            for r in batch:
+                r.future.set_exception(e)
+            self.free_slots.append(slot)
+            return True
+        self.inflight.append((slot, handle, batch, nbytes))
+        self.bytes_in_flight += nbytes
+        st = self.stats
+        st["admitted"] += len(batch)
+        st["launches"] += 1
+        st["max_bytes_in_flight"] = max(st["max_bytes_in_flight"], self.bytes_in_flight)
+        st["max_concurrent_launches"] = max(st["max_concurrent_launches"], len(self.inflight))
+        return True
+
+    def _loop(self):
+        while True:
+            self._drain_incoming()
+            self._complete()
+            launched = self._admit_and_launch()
+            if self._stop.is_set() and not self.inflight and not self.waiting and self.incoming.empty():
+                break
+            if not launched:
+                time.sleep(self.idle_sleep)
+
+
+def percentiles(latencies, qs=(50, 99)):
+    a = np.sort(np.asarray(latencies))
+    return {"p%d" % q: float(a[min(len(a) - 1, int(math.ceil(q / 100.0 * len(a))) - 1)]) for q in qs}

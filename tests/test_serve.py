@@ -1,0 +1,132 @@
+"""Scheduler of the serving loop on the CPU: a fake backend (the oracle, with a
+simulated device duration) stands in for the GPU.  Checks HBM-budget admission,
+rejection of oversized requests, queueing until memory frees up, overlap of
+launches (continuous batching) and that every future gets its own result."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_00443_amd import synth
+from paper_1703_00443_amd.serve import RejectedError, Server, footprint_bytes, percentiles
+
+
+class FakeBackend:
+    esz = 8
+
+    def __init__(self, delay=0.02):
+        self.delay = delay
+        self.launched = []
+        self.active = 0
+        self.max_active = 0
+        self.lock = threading.Lock()
+
+    def new_slot(self):
+        return object()
+
+    def launch(self, slot, reqs):
+        res = []
+        for r in reqs:
+            P = r.problem
+            o = oracle.solve(P["Q"], P["q"], P.get("A"), P.get("b"), P.get("G"), P.get("h"))
+            out = {"z": o["z"], "lam": o["lam"], "nu": o["nu"], "s": o["s"], "status": o["status"],
+                   "iters": o["iters"]}
+            if r.need_backward:
+                g = oracle.backward(P["Q"], P.get("A"), P.get("G"), P.get("h"), o["z"], o["lam"],
+                                    o["nu"], r.dl_dz)
+                out.update({k: g[k] for k in ("dQ", "dq", "dA", "db", "dG", "dh")})
+            res.append(out)
+        with self.lock:
+            self.active += 1
+            self.max_active = max(self.max_active, self.active)
+        self.launched.append([r.dims for r in reqs])
+        return {"t": time.perf_counter() + self.delay, "res": res, "done": False}
+
+    def ready(self, h):
+        ok = time.perf_counter() >= h["t"]
+        if ok and not h["done"]:
+            h["done"] = True
+            with self.lock:
+                self.active -= 1
+        return ok
+
+    def collect(self, h, reqs):
+        return h["res"]
+
+
+def _problems(k, seed=3):
+    dims = [(4 + i % 5, 6 + i % 7, i % 2) for i in range(k)]
+    return synth.make_varlen(seed, dims), dims
+
+
+def test_each_future_gets_its_own_result():
+    probs, dims = _problems(12)
+    srv = Server(backend=FakeBackend(0.005), hbm_budget=1 << 30, max_inflight=2)
+    futs = [srv.submit(P, need_backward=bool(i % 2), dl_dz=P["g"]) for i, P in enumerate(probs)]
+    res = [f.result(timeout=30) for f in futs]
+    srv.close()
+    for i, (P, r) in enumerate(zip(probs, res)):
+        o = oracle.solve(P["Q"], P["q"], P["A"], P["b"], P["G"], P["h"])
+        np.testing.assert_array_equal(r["z"], o["z"])
+        assert ("dQ" in r) == bool(i % 2)
+        assert r["latency"] > 0
+
+
+def test_oversized_request_is_rejected():
+    probs, _ = _problems(1)
+    P = probs[0]
+    n = P["Q"].shape[0]
+    need = footprint_bytes(n, P["G"].shape[0], P["A"].shape[0], 8, False)
+    srv = Server(backend=FakeBackend(), hbm_budget=need - 1, max_inflight=1)
+    f = srv.submit(P)
+    with pytest.raises(RejectedError):
+        f.result(timeout=5)
+    srv.close()
+    assert srv.stats["rejected"] == 1
+
+
+def test_budget_bounds_bytes_in_flight_and_queues_the_rest():
+    probs, dims = _problems(20)
+    fps = [footprint_bytes(d[0], d[1], d[2], 8, False) for d in dims]
+    budget = 3 * max(fps)  # room for about three requests at a time
+    be = FakeBackend(0.03)
+    srv = Server(backend=be, hbm_budget=budget, max_inflight=4)
+    futs = [srv.submit(P) for P in probs]
+    for f in futs:
+        f.result(timeout=60)
+    srv.close()
+    assert srv.stats["max_bytes_in_flight"] <= budget
+    assert srv.stats["admitted"] == 20
+    assert srv.stats["max_queue"] > 0           # some requests had to wait for memory
+    assert srv.stats["launches"] >= 6           # ... and went out in later launches
+
+
+def test_arrivals_during_flight_overlap_launches():
+    """Requests that arrive while a launch is in flight start in a new launch on a
+    free slot before the earlier one completes (continuous batching)."""
+    probs, _ = _problems(8)
+    be = FakeBackend(0.2)
+    srv = Server(backend=be, hbm_budget=1 << 30, max_inflight=4)
+    f0 = srv.submit(probs[0])
+    time.sleep(0.05)
+    f1 = srv.submit(probs[1])
+    f1.result(timeout=10)
+    f0.result(timeout=10)
+    srv.close()
+    assert be.max_active >= 2
+    assert srv.stats["max_concurrent_launches"] >= 2
+
+
+def test_backward_needs_upstream_gradient():
+    probs, _ = _problems(1)
+    srv = Server(backend=FakeBackend(), max_inflight=1)
+    with pytest.raises(ValueError):
+        srv.submit(probs[0], need_backward=True).result(timeout=5)
+    srv.close()
+
+
+def test_percentiles():
+    p = percentiles(list(range(1, 101)))
+    assert p["p50"] == 50 and p["p99"] == 99
