@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 METRIC = "QP solves/s fwd+bwd (B=128,n=m=100) vs plain; p50/p99 latency in serving"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X published dense peaks (vector = matrix)
 HBM_GBS = 8000.0
-KERNEL_SOURCES = ("qp_core.hpp", "qp_ipm.hpp", "qp_policies.hpp", "qp_forward.hip")
+KERNEL_SOURCES = ("qp_core.hpp", "qp_ipm.hpp", "qp_policies.hpp", "qp_forward.hpp", "qp_forward.hip",
+                  "qp_forward_f32.hip", "qp_forward_f64.hip")
 
 
 def algorithmic_flops(n, m, p, iters):
@@ -276,7 +277,7 @@ def main():
                                "row-normalised G, fwd+bwd",
                    "batch": B, "nz": n, "nineq": m, "neq": p,
                    "tol": opts.tol, "max_iter": opts.max_iter, "refine_steps": opts.refine_steps},
-        "roofline": {"kernel": "qp_forward_kernel", "bound": "mfma", "achieved": round(achieved, 4),
+        "roofline": {"kernel": "qp_forward_uniform_kernel", "bound": "mfma", "achieved": round(achieved, 4),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
                      "traffic": traffic,
                      "flops_per_launch": flops, "launch_ms": round(fwd_ms, 4)},

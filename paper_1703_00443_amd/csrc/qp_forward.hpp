@@ -1,0 +1,170 @@
+// Forward kernels: the interior point method of Section 3.1 for a batch of
+// QPs, one workgroup (512 threads, eight wavefronts) per problem, the whole
+// solve (initial point, Newton loop, stored factor) in one launch.
+//
+// * Uniform batch (every problem has the same dims, hence the same plan): one
+//   kernel per factorization policy with the solve inlined.
+// * Uneven batch: one persistent kernel over a work queue; each workgroup
+//   picks the policy of the problem it takes from that problem's own dims and
+//   runs it as an out-of-line call, so that each policy keeps its own
+//   register allocation.
+//
+// Included by one translation unit per element type.
+#pragma once
+#include "qp_policies.hpp"
+
+namespace qpmi {
+
+constexpr int kFwdThreads = 64 * kTiledWaves;
+
+__host__ __device__ inline int plan_policy(int esz, int n, int m, int p, int variant, int lds_limit,
+                                           int *lds_bytes) {
+    const int base = IpmLayout(n, m, p).end;
+    if (variant == QP_VARIANT_AUTO || variant == QP_VARIANT_TILED) {
+        if (n <= kTiledMaxN) {
+            const int gl = TiledLayout<true>(base, n, m, p).end * esz;
+            if (gl <= lds_limit) { *lds_bytes = gl; return kPolicyTiledGLds; }
+            const int gg = TiledLayout<false>(base, n, m, p).end * esz;
+            if (gg <= lds_limit) { *lds_bytes = gg; return kPolicyTiledGGlobal; }
+        } else if (esz == 4 && n <= kTiledBigMaxN) {
+            const int gg = TiledLayout<false>(base, n, m, p).end * esz;
+            if (gg <= lds_limit) { *lds_bytes = gg; return kPolicyTiledBig; }
+        }
+    }
+    if (variant != QP_VARIANT_GENERIC) {
+        const int hl = GenericLayout<true>(base, n, m, p).end * esz;
+        if (hl <= lds_limit) { *lds_bytes = hl; return kPolicyGenericLds; }
+    }
+    const int gg = GenericLayout<false>(base, n, m, p).end * esz;
+    if (gg <= lds_limit) { *lds_bytes = gg; return kPolicyGenericGlobal; }
+    *lds_bytes = gg;
+    return kPolicyNone;
+}
+
+// One problem under one policy, out of line (uneven batches).
+template <typename T, class F>
+__device__ __noinline__ void run_policy(const Prob<T> P, T *sm, const FwdLaunch &L) {
+    const IpmLayout Lo(P.n, P.m, P.p);
+    F f(P, sm, Lo.end);
+    ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
+}
+
+template <typename T, bool EQ>
+__device__ __forceinline__ void run_tiled(int pol, const Prob<T> &P, T *sm, const FwdLaunch &L) {
+    if (pol == kPolicyTiledGLds) {
+        run_policy<T, TiledFactor<T, true, 8, EQ>>(P, sm, L);
+    } else if (pol == kPolicyTiledGGlobal) {
+        run_policy<T, TiledFactor<T, false, 8, EQ>>(P, sm, L);
+    } else if constexpr (sizeof(T) == 4) {
+        run_policy<T, TiledFactor<T, false, 16, EQ>>(P, sm, L);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunch L) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int next_idx;
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    int idx = blockIdx.x;
+    for (;;) {
+        if (L.queue) {
+            // work queue: problems are taken in `order` (largest first) as
+            // workgroups free up; every workgroup exits once the queue is empty
+            if (threadIdx.x == 0) next_idx = atomicAdd(L.queue, 1);
+            __syncthreads();
+            idx = next_idx;
+            __syncthreads();
+        }
+        if (idx >= L.count) break;
+        const Prob<T> P = fwd_problem<T>(L, idx);
+        int bytes = 0;
+        const int pol = plan_policy(sizeof(T), P.n, P.m, P.p, P.variant, L.lds_limit, &bytes);
+        if (pol == kPolicyTiledGLds || pol == kPolicyTiledGGlobal || pol == kPolicyTiledBig) {
+            if (P.p > 0) run_tiled<T, true>(pol, P, sm, L);
+            else run_tiled<T, false>(pol, P, sm, L);
+        } else if (pol == kPolicyGenericLds) {
+            run_policy<T, GenericFactor<T, kFwdThreads, true>>(P, sm, L);
+        } else {
+            run_policy<T, GenericFactor<T, kFwdThreads, false>>(P, sm, L);
+        }
+        if (!L.queue) idx += gridDim.x;
+    }
+}
+
+// Uniform batch: the plan is the same for every problem, so the launch runs
+// one policy with the solve inlined.
+template <typename T, class F>
+__global__ __launch_bounds__(kFwdThreads) void qp_forward_uniform_kernel(FwdLaunch L) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    for (int idx = blockIdx.x; idx < L.count; idx += gridDim.x) {
+        const Prob<T> P = fwd_problem<T>(L, idx);
+        const IpmLayout Lo(P.n, P.m, P.p);
+        F f(P, sm, Lo.end);
+        ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
+    }
+}
+
+template <class K>
+static void set_lds_limit_once(K kern, int lds_limit) {
+    static bool done = false;
+    if (!done) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
+        done = true;
+    }
+}
+
+template <typename T, class F>
+static hipError_t launch_uniform(const FwdLaunch &L, hipStream_t st) {
+    auto kern = qp_forward_uniform_kernel<T, F>;
+    set_lds_limit_once(kern, L.lds_limit);
+    hipLaunchKernelGGL(kern, dim3(L.count), dim3(kFwdThreads), L.lds_bytes, st, L);
+    return hipGetLastError();
+}
+
+template <typename T, bool EQ>
+static hipError_t launch_uniform_tiled(int pol, const FwdLaunch &L, hipStream_t st) {
+    if (pol == kPolicyTiledGLds) return launch_uniform<T, TiledFactor<T, true, 8, EQ>>(L, st);
+    if (pol == kPolicyTiledGGlobal) return launch_uniform<T, TiledFactor<T, false, 8, EQ>>(L, st);
+    if constexpr (sizeof(T) == 4) return launch_uniform<T, TiledFactor<T, false, 16, EQ>>(L, st);
+    return hipErrorInvalidValue;
+}
+
+__global__ void qp_zero_counter_kernel(int *c);
+
+template <typename T>
+hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
+    if (L.count <= 0) return hipSuccess;
+    if (L.desc == nullptr) {
+        int bytes = 0;
+        const int pol = plan_policy(sizeof(T), L.nz, L.nineq, L.neq, L.variant, L.lds_limit, &bytes);
+        if (pol == kPolicyTiledGLds || pol == kPolicyTiledGGlobal || pol == kPolicyTiledBig)
+            return L.neq > 0 ? launch_uniform_tiled<T, true>(pol, L, st)
+                             : launch_uniform_tiled<T, false>(pol, L, st);
+        if (pol == kPolicyGenericLds) return launch_uniform<T, GenericFactor<T, kFwdThreads, true>>(L, st);
+        return launch_uniform<T, GenericFactor<T, kFwdThreads, false>>(L, st);
+    }
+    auto kern = qp_forward_varlen_kernel<T>;
+    set_lds_limit_once(kern, L.lds_limit);
+    if (L.queue) {
+        hipLaunchKernelGGL(qp_zero_counter_kernel, dim3(1), dim3(1), 0, st, L.queue);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int grid = L.grid > 0 ? L.grid : L.count;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kFwdThreads), L.lds_bytes, st, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+int resident_t(int lds_bytes) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T>, kFwdThreads,
+                                                     (size_t)lds_bytes) != hipSuccess || per < 1)
+        per = 1;
+    return cus * per;
+}
+
+}  // namespace qpmi

@@ -121,6 +121,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         fin = bad == T(0);
     }
     int st = QP_STATUS_MAX_ITER, it = 0;
+    bool stalled = false;  // re-running the previous iterate after a breakdown
     if (!fin) {
         st = QP_STATUS_NONFINITE;
         for (int e = tid; e < n; e += NT) z[e] = 0;
@@ -217,17 +218,19 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         const bool ok = finite_now && fac.factor(D);
 
         if (!finite_now) { st = QP_STATUS_NONFINITE; break; }
+        if (stalled) { st = ok ? QP_STATUS_STALLED : QP_STATUS_BREAKDOWN; break; }
         if (!ok) {
             if (it == 0) { st = QP_STATUS_BREAKDOWN; break; }
-            // working precision exhausted: return the previous iterate, whose
-            // factorization succeeded, with that factor stored
+            // working precision exhausted: go back to the previous iterate,
+            // whose factorization succeeded, and return it with that factor
+            // (recomputed by the same code, so identical); one factor call site
             for (int i = tid; i < n; i += NT) z[i] = zp[i];
-            for (int k = tid; k < m; k += NT) { s[k] = sp[k]; lam[k] = lp[k]; D[k] = lp[k] / sp[k]; }
+            for (int k = tid; k < m; k += NT) { s[k] = sp[k]; lam[k] = lp[k]; }
             for (int k = tid; k < p; k += NT) nu[k] = nup[k];
             __syncthreads();
-            --it;
-            st = fac.factor(D) ? QP_STATUS_STALLED : QP_STATUS_BREAKDOWN;
-            break;
+            stalled = true;
+            it -= 2;
+            continue;
         }
         if (err <= tol) { st = QP_STATUS_OPTIMAL; break; }
         if (it >= max_iter) { st = QP_STATUS_MAX_ITER; break; }

@@ -3,11 +3,13 @@
 // GenericFactor: the factor lives in LDS (HL) or in the global state buffer;
 //   plain per-element loops; any size; any number of equality rows.
 // TiledFactor: the padded square of 16x16 tiles lives in the registers of
-//   four wavefronts in the MFMA accumulator layout; H = Qs + G^T D G is formed
-//   with v_mfma_*_16x16x4; the Cholesky factorisation and the triangular
-//   inverse are one sequence of rank-1 updates (one barrier per column);
-//   the triangular solves are register matrix-vector products.  nz <= 128,
-//   neq == 0; G is staged in LDS when it fits (GL).
+//   eight wavefronts in the MFMA accumulator layout; H = Qs + G^T D G is
+//   formed with v_mfma_*_16x16x4 from G in LDS (resident, or staged in
+//   chunks); the Cholesky factorisation and the triangular inverse are one
+//   blocked sequence (diagonal tile chain, MFMA panel and trailing updates);
+//   the Schur complement on A is two MFMA products and a small LDS
+//   factorisation; the triangular solves are register matrix-vector products.
+//   nz <= 128 (NTL = 8), or nz <= 256 in FP32 (NTL = 16).
 #pragma once
 #include "qp_ipm.hpp"
 
@@ -15,9 +17,11 @@ namespace qpmi {
 
 __host__ __device__ inline int h_ld(int n) { return n | 1; }
 
-// The padded square is an 8x8 grid of 16x16 tiles (nz <= 128).  Wavefront w
-// owns tile (s, (w - s) mod 8) in its register slot s: one tile per tile row,
-// spread along anti-diagonals so that the lower triangle is shared evenly.
+// The padded square is an NTL x NTL grid of 16x16 tiles (nz <= 16 NTL, NTL =
+// 8 or 16) spread over eight wavefronts: tile (I, J) lives in wavefront
+// (I + J) mod 8, so every wavefront holds NTL / 8 tiles of each tile row and
+// the lower triangle is shared evenly.  Register slot s of wavefront w holds
+// tile (s / H, ((w - s / H) mod 8) + 8 (s mod H)), H = NTL / 8.
 constexpr int kTiledWaves = 8;
 
 // The lane id through an opaque move: index arithmetic derived from it is
@@ -28,8 +32,9 @@ __device__ __forceinline__ int opaque_tid() {
     asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
     return t;
 }
-constexpr int kTiledSlots = 8;
-constexpr int kTiledMaxN = 128;
+constexpr int kTiledMaxN = 128;      // NTL = 8 (FP32 and FP64)
+constexpr int kTiledBigMaxN = 256;   // NTL = 16 (FP32 only: 32 register tiles per wavefront)
+constexpr int kGChunk = 32;          // rows of G staged per LDS chunk when G is not LDS-resident
 
 // LDS regions of the policies (elements of T, after the driver's vectors).
 template <bool HL>
@@ -47,20 +52,25 @@ struct GenericLayout {
     }
 };
 
+// GL: all of G resident in LDS (rows padded to a multiple of 4, ld 16 nt + 1);
+// otherwise a staging buffer of kGChunk rows.  S: the Schur complement block
+// (ld p | 1) with its pivot scratch and two p-vectors.
 template <bool GL>
 struct TiledLayout {
-    int colbuf, part, yv, xv, panel, scratch, dbuf, flag, G, end;
-    __host__ __device__ TiledLayout(int base, int n, int m) {
+    int part, yv, xv, panel, scratch, dbuf, flag, S, xdp, pv1, pv2, G, end;
+    __host__ __device__ TiledLayout(int base, int n, int m, int p) {
         const int nt = (n + 15) / 16, np = 16 * nt;
         int o = base;
-        colbuf = o; o += 2 * np; part = o; o += nt * np; yv = o; o += np; xv = o; o += np;
+        part = o; o += nt * np; yv = o; o += np; xv = o; o += np;
         panel = o; o += np * 17;
         scratch = o; o += 64 * kTiledWaves;
         dbuf = o; o += 16;
         flag = o; o += 4;
+        S = o; o += p > 0 ? p * h_ld(p) : 0;
+        xdp = o; o += pad4(p); pv1 = o; o += pad4(p); pv2 = o; o += pad4(p);
         o = (o + 15) & ~15;
         G = o;
-        end = GL ? o + ((m + 3) & ~3) * (np + 1) : o;
+        end = o + (GL ? ((m + 3) & ~3) : kGChunk) * (np + 1);
     }
 };
 
@@ -162,21 +172,34 @@ struct Mfma<float> {
 
 
 
-template <typename T, bool GL>
+// Which tiles a wavefront holds (see the grid comment above).
+template <int NTL>
+struct TileMap {
+    static constexpr int H = NTL / 8;    // tiles per tile row in one wavefront
+    static constexpr int NS = NTL * H;   // register slots per wavefront
+    __device__ static __forceinline__ int row(int s) { return s / H; }
+    __device__ static __forceinline__ int col(int w, int s) { return ((w - s / H) & 7) + 8 * (s % H); }
+    __device__ static __forceinline__ int diag_slot(int P) { return P * H + (P >> 3); }
+};
+
+// EQ: the problem has equality rows (Schur complement on A).  Instantiated
+// separately so that the no-equality solve carries none of that code.
+template <typename T, bool GL, int NTL, bool EQ>
 struct TiledFactor {
     static constexpr int NT = 64 * kTiledWaves;
+    static constexpr int NS = TileMap<NTL>::NS;
     using v4 = typename Mfma<T>::v4;
-    int n, m, p, nt, np, ldg;
-    const T *Q, *Gsrc;
-    const T *G;  // LDS copy (GL) or global
-    T *Qs;       // Qs, then the factor, in the state buffer (row-major, ld n)
-    T *Dst;
-    T *colbuf, *part, *yv, *xv, *panel, *scratch, *dbuf;
+    int n, m, p, nt, np, pt, ldg, lds;
+    const T *Q, *Gsrc, *A;
+    const T *G;  // LDS copy (GL) or the staging chunk
+    T *Ust, *Dst, *Wt, *US;  // state: U (row-major, ld n), D, Wt (p x n), US (p x p)
+    T *part, *yv, *xv, *panel, *scratch, *dbuf, *S, *xdp, *pv1, *pv2;
     int *flag;
     int w, lane, g, c;
-    v4 sq[kTiledSlots];
+    v4 sq[NS];
 
-    __device__ __forceinline__ int tcol(int s) const { return (w - s) & 7; }
+    __device__ __forceinline__ int trow(int s) const { return TileMap<NTL>::row(s); }
+    __device__ __forceinline__ int tcol(int s) const { return TileMap<NTL>::col(w, s); }
     __device__ __forceinline__ void lane_ids() {
         const int t = opaque_tid();
         lane = t & 63; g = lane >> 4; c = lane & 15;
@@ -185,109 +208,102 @@ struct TiledFactor {
 
     __device__ TiledFactor(const Prob<T> &P, T *sm, int base) {
         n = P.n; m = P.m; p = P.p;
-        nt = (n + 15) / 16; np = 16 * nt;
-        Q = P.Q; Gsrc = P.G;
+        nt = (n + 15) / 16; np = 16 * nt; pt = (p + 15) / 16;
+        Q = P.Q; Gsrc = P.G; A = P.A;
         const StateLayout SL = state_layout(sizeof(T), n, m, p);
-        Qs = (T *)(P.state + SL.off_U);
+        Ust = (T *)(P.state + SL.off_U);
         Dst = (T *)(P.state + SL.off_D);
-        const TiledLayout<GL> L(base, n, m);
-        colbuf = sm + L.colbuf; part = sm + L.part; yv = sm + L.yv; xv = sm + L.xv;
+        Wt = (T *)(P.state + SL.off_Wt);
+        US = (T *)(P.state + SL.off_US);
+        const TiledLayout<GL> L(base, n, m, p);
+        part = sm + L.part; yv = sm + L.yv; xv = sm + L.xv;
         panel = sm + L.panel; scratch = sm + L.scratch; dbuf = sm + L.dbuf;
+        S = sm + L.S; xdp = sm + L.xdp; pv1 = sm + L.pv1; pv2 = sm + L.pv2;
         flag = reinterpret_cast<int *>(sm + L.flag);
-        if (GL) { G = sm + L.G; ldg = np + 1; } else { G = Gsrc; ldg = n; }
+        G = sm + L.G; ldg = np + 1; lds = h_ld(p);
         lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
     }
 
+    // Rows [k0, k0 + rows) of G into the LDS buffer, zero-padded to whole MFMA
+    // steps (rows to a multiple of 4, columns to 16 nt).
+    __device__ __forceinline__ void stage_g(int k0, int rows) {
+        const int rp = (rows + 3) & ~3;
+        T *dst = const_cast<T *>(G);
+        for (int e = threadIdx.x; e < rp * np; e += NT) {
+            const int k = e / np, i = e - k * np;
+            dst[k * ldg + i] = (k < rows && i < n) ? Gsrc[(size_t)(k0 + k) * n + i] : T(0);
+        }
+    }
+
+    // Without equality rows the U region of the state is free until finish():
+    // it holds Qs = (Q + Q^T) / 2 for coalesced single loads in form() and
+    // qs_mv().  With equality rows the Schur step stores U there every
+    // factorization, and Qs is taken from Q itself.
     __device__ __forceinline__ void prepare() {
-        for (int e = threadIdx.x; e < n * n; e += NT) {
-            const int i = e / n, j = e - i * n;
-            Qs[e] = T(0.5) * (Q[(size_t)i * n + j] + Q[(size_t)j * n + i]);
-        }
-        if (GL) {
-            // zero-padded to whole MFMA steps: rows to a multiple of 4, columns to 16*nt
-            const int mp = (m + 3) & ~3;
-            for (int e = threadIdx.x; e < mp * ldg; e += NT) {
-                const int k = e / ldg, i = e - k * ldg;
-                const_cast<T *>(G)[e] = (k < m && i < n) ? Gsrc[(size_t)k * n + i] : T(0);
+        if (!EQ)
+            for (int e = threadIdx.x; e < n * n; e += NT) {
+                const int i = e / n, j = e - i * n;
+                Ust[e] = T(0.5) * (Q[(size_t)i * n + j] + Q[(size_t)j * n + i]);
             }
-        }
+        if (GL) stage_g(0, m);
         __syncthreads();
     }
 
     // H = Qs + G^T D G into the register tiles (lower tiles), X region zero.
-    // Accumulators start from Qs (identity on the padding); the k loop runs
-    // outside the tile loop so that the MFMAs of the tiles of a wavefront are
-    // independent and overlap their operand loads.
+    // Accumulators start from Qs = (Q + Q^T) / 2 (identity on the padding); the
+    // k loop runs outside the tile loop so that the MFMAs of the tiles of a
+    // wavefront are independent and overlap their operand loads.
     __device__ __forceinline__ void form(const T *D) {
         lane_ids();
 #pragma unroll
-        for (int s = 0; s < kTiledSlots; ++s) {
-            const int I = s, J = tcol(s);
+        for (int s = 0; s < NS; ++s) {
+            const int I = trow(s), J = tcol(s);
             v4 acc = {0, 0, 0, 0};
             if (I < nt && J < nt && I >= J) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = 16 * I + Mfma<T>::row(g, r), col = 16 * J + c;
                     const bool in = row < n && col < n;
-                    const T qv = Qs[in ? (size_t)row * n + col : 0];
-                    acc[r] = in ? qv : (row == col ? T(1) : T(0));
+                    T qs;
+                    if (!EQ) {
+                        qs = Ust[in ? (size_t)row * n + col : 0];
+                    } else {
+                        const T qa = Q[in ? (size_t)row * n + col : 0];
+                        const T qb = Q[in ? (size_t)col * n + row : 0];
+                        qs = T(0.5) * (qa + qb);
+                    }
+                    acc[r] = in ? qs : (row == col ? T(1) : T(0));
                 }
             }
             sq[s] = acc;
         }
-        if (GL) {
-            // padded LDS copy of G: straight-line operand loads, no masks
-            for (int kb = 0; kb < m; kb += 4) {
+        for (int k0 = 0; k0 < m; k0 += (GL ? m : kGChunk)) {
+            const int rows = GL ? m : min(kGChunk, m - k0);
+            if (!GL) {
+                __syncthreads();  // previous chunk consumed
+                stage_g(k0, rows);
+                __syncthreads();
+                lane_ids();
+            }
+            for (int kb = 0; kb < rows; kb += 4) {
                 const int k = kb + g;
                 const T *Gk = G + (size_t)k * ldg;
-                const T dk = D[k < m ? k : m - 1] * T(k < m ? 1 : 0);
+                const int kg = k0 + k;
+                const T dk = D[kg < m ? kg : m - 1] * T(kg < m ? 1 : 0);
 #pragma unroll
-                for (int s = 0; s < kTiledSlots; ++s) {
-                    const int I = s, J = tcol(s);
+                for (int s = 0; s < NS; ++s) {
+                    const int I = trow(s), J = tcol(s);
                     if (I >= nt || J >= nt || I < J) continue;
                     sq[s] = Mfma<T>::mma(Gk[16 * I + c], dk * Gk[16 * J + c], sq[s]);
                 }
             }
-        } else {
-            for (int kb = 0; kb < m; kb += 4) {
-                const int k = kb + g;
-                const bool vk = k < m;
-                const T *Gk = G + (size_t)(vk ? k : 0) * ldg;
-                const T dk = vk ? D[k] : T(0);
-#pragma unroll
-                for (int s = 0; s < kTiledSlots; ++s) {
-                    const int I = s, J = tcol(s);
-                    if (I >= nt || J >= nt || I < J) continue;
-                    const int ci = 16 * I + c, cj = 16 * J + c;
-                    const T ga = Gk[ci < n ? ci : 0];
-                    const T gb = Gk[cj < n ? cj : 0];
-                    const T a = (vk && ci < n) ? ga : T(0);
-                    const T b = (cj < n) ? dk * gb : T(0);
-                    sq[s] = Mfma<T>::mma(a, b, sq[s]);
-                }
-            }
         }
 #pragma unroll
-        for (int s = 0; s < kTiledSlots; ++s) {
-            if (s >= nt || tcol(s) != s) continue;
+        for (int s = 0; s < NS; ++s) {
+            if (trow(s) >= nt || tcol(s) != trow(s)) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 if (Mfma<T>::row(g, r) < c) sq[s][r] = T(0);  // X part of the diagonal tile
-        }
-    }
-
-    // Publish column kk of the square to colbuf[kk & 1].
-    __device__ __forceinline__ void publish(int kk) {
-        T *buf = colbuf + (kk & 1) * np;
-        const int Jk = kk >> 4, ck = kk & 15;
-#pragma unroll
-        for (int s = 0; s < kTiledSlots; ++s) {
-            const int I = s, J = tcol(s);
-            if (I >= nt || J >= nt) continue;
-            if (J == Jk && c == ck) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) buf[16 * I + Mfma<T>::row(g, r)] = sq[s][r];
-            }
         }
     }
 
@@ -314,20 +330,22 @@ struct TiledFactor {
         __syncthreads();
         for (int P = 0; P < nt; ++P) {
             lane_ids();
-            const int wd = (2 * P) & 7;  // owner of the diagonal tile (P,P), slot P
+            const int wd = (2 * P) & 7;  // owner of the diagonal tile (P,P)
+            const int sd = TileMap<NTL>::diag_slot(P);
             // ---- (1a) old panel tiles (R != P) to LDS, ld 17
 #pragma unroll
-            for (int s = 0; s < kTiledSlots; ++s) {
-                if (s >= nt || s == P || tcol(s) != P) continue;
+            for (int s = 0; s < NS; ++s) {
+                const int R = trow(s);
+                if (R >= nt || R == P || tcol(s) != P) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) panel[(16 * s + Mfma<T>::row(g, r)) * 17 + c] = sq[s][r];
+                for (int r = 0; r < 4; ++r) panel[(16 * R + Mfma<T>::row(g, r)) * 17 + c] = sq[s][r];
             }
             // ---- (1b) the diagonal tile, 16 dependent steps in one wavefront
             if (w == wd) {
                 v4 t = {0, 0, 0, 0};
 #pragma unroll
-                for (int s = 0; s < kTiledSlots; ++s)
-                    if (s == P) t = sq[s];
+                for (int s = 0; s < NS; ++s)
+                    if (s == sd) t = sq[s];
                 int rl[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) rl[r] = Mfma<T>::row(g, r);
@@ -364,8 +382,8 @@ struct TiledFactor {
                 }
                 if (bad && c == 0 && g == 0) *flag = 1;
 #pragma unroll
-                for (int s = 0; s < kTiledSlots; ++s)
-                    if (s == P) sq[s] = t;
+                for (int s = 0; s < NS; ++s)
+                    if (s == sd) sq[s] = t;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) panel[(16 * P + rl[r]) * 17 + c] = t[r];
             }
@@ -374,13 +392,14 @@ struct TiledFactor {
             // ---- (2) panel tiles R != P:  tile <- tile * X_PP^T
             lane_ids();
 #pragma unroll
-            for (int s = 0; s < kTiledSlots; ++s) {
-                if (s >= nt || s == P || tcol(s) != P) continue;
+            for (int s = 0; s < NS; ++s) {
+                const int R = trow(s);
+                if (R >= nt || R == P || tcol(s) != P) continue;
                 v4 d = {0, 0, 0, 0};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int kq = 4 * q + g;
-                    const T a = panel[(16 * s + c) * 17 + kq];
+                    const T a = panel[(16 * R + c) * 17 + kq];
                     // X_PP^T[kq][c] sits in the upper triangle (incl. diagonal) of tile (P,P)
                     const T bx = panel[(16 * P + kq) * 17 + c];
                     const T b = (kq <= c) ? bx : T(0);
@@ -388,14 +407,14 @@ struct TiledFactor {
                 }
                 sq[s] = d;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) panel[(16 * s + Mfma<T>::row(g, r)) * 17 + c] = d[r];
+                for (int r = 0; r < 4; ++r) panel[(16 * R + Mfma<T>::row(g, r)) * 17 + c] = d[r];
             }
             __syncthreads();
             if (P + 1 == nt) break;
             // ---- (3) rank-16 update of the tiles right of the panel
 #pragma unroll
-            for (int s = 0; s < kTiledSlots; ++s) {
-                const int R = s, C = tcol(s);
+            for (int s = 0; s < NS; ++s) {
+                const int R = trow(s), C = tcol(s);
                 if (R >= nt || C >= nt || C <= P) continue;
                 if (R > P && R < C) continue;  // rows of X below the panel: no step applies
                 v4 d = {0, 0, 0, 0};
@@ -419,18 +438,87 @@ struct TiledFactor {
         return true;
     }
 
-    __device__ __forceinline__ bool factor(const T *D) {
-        form(D);
-        return chol_inv();
-    }
-
-    // y = U^T f then dz = U y with U = L^{-T} in the upper register tiles.
-    __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
-        (void)r4; (void)dnu;
+    // U (upper register tiles, incl. diagonal) to the state, row-major ld n.
+    __device__ __forceinline__ void store_u() {
         lane_ids();
 #pragma unroll
-        for (int s = 0; s < kTiledSlots; ++s) {
-            const int I = s, J = tcol(s);
+        for (int s = 0; s < NS; ++s) {
+            const int I = trow(s), J = tcol(s);
+            if (I >= nt || J >= nt || I > J) continue;
+            const int col = 16 * J + c;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * I + Mfma<T>::row(g, r);
+                if (row <= col && row < n && col < n) Ust[(size_t)row * n + col] = sq[s][r];
+            }
+        }
+    }
+
+    // Schur complement on A (neq > 0): Wt = A U (MFMA tiles over the stored
+    // U, a p x n product), S = Wt Wt^T (lower triangle, LDS), S = LS LS^T with
+    // its inverse factor in place.
+    __device__ __forceinline__ bool schur() {
+        store_u();
+        __syncthreads();
+        lane_ids();
+        for (int t = w; t < pt * nt; t += kTiledWaves) {
+            const int K = t / nt, J = t - K * nt;
+            const int arow = 16 * K + c, col = 16 * J + c;
+            const int kend = min(n, 16 * J + 16);  // U[k][col] = 0 for k > col
+            v4 d = {0, 0, 0, 0};
+            for (int kb = 0; kb < kend; kb += 4) {
+                const int k = kb + g;
+                const bool ka = arow < p && k < n, kbv = k < n && col < n && k <= col;
+                const T av = A[ka ? (size_t)arow * n + k : 0];
+                const T bv = Ust[kbv ? (size_t)k * n + col : 0];
+                d = Mfma<T>::mma(ka ? av : T(0), kbv ? bv : T(0), d);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * K + Mfma<T>::row(g, r);
+                if (row < p && col < n) Wt[(size_t)row * n + col] = d[r];
+            }
+        }
+        __syncthreads();
+        lane_ids();
+        for (int t = w; t < pt * pt; t += kTiledWaves) {
+            const int K = t / pt, Lb = t - K * pt;
+            const int ra = 16 * K + c, rb = 16 * Lb + c;
+            v4 d = {0, 0, 0, 0};
+            if (Lb <= K) {
+                for (int kb = 0; kb < n; kb += 4) {
+                    const int k = kb + g;
+                    const bool va = ra < p && k < n, vb = rb < p && k < n;
+                    const T av = Wt[va ? (size_t)ra * n + k : 0];
+                    const T bv = Wt[vb ? (size_t)rb * n + k : 0];
+                    d = Mfma<T>::mma(va ? av : T(0), vb ? bv : T(0), d);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * K + Mfma<T>::row(g, r), col = 16 * Lb + c;
+                if (row < p && col < p) S[row * lds + col] = (col <= row) ? d[r] : T(0);
+            }
+        }
+        __syncthreads();
+        return ::qpmi::chol_inv<T, NT>(S, lds, p, xdp);
+    }
+
+    __device__ __forceinline__ bool factor(const T *D) {
+        form(D);
+        if (!chol_inv()) return false;
+        if constexpr (EQ) return schur();
+        return true;
+    }
+
+    // [H A^T; A 0][dz; dnu] = [f; r4] with U = L^{-T} in the upper register
+    // tiles:  y = U^T f;  (p > 0) dnu = US US^T (Wt y - r4), y -= Wt^T dnu;
+    // dz = U y.
+    __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
+        lane_ids();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int I = trow(s), J = tcol(s);
             if (I >= nt || J >= nt) continue;
             if (I > J) continue;
             const int col = 16 * J + c;
@@ -452,9 +540,26 @@ struct TiledFactor {
             yv[col] = acc;
         }
         __syncthreads();
+        if constexpr (EQ) {
+            mv_rows<T, NT>(Wt, n, p, n, yv, pv1);
+            __syncthreads();
+            for (int k = threadIdx.x; k < p; k += NT) pv1[k] -= r4[k];
+            __syncthreads();
+            ut_mv<T, NT>(S, lds, p, pv1, pv2);
+            __syncthreads();
+            u_mv<T, NT>(S, lds, p, pv2, dnu);
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += NT) {
+                T acc = yv[i];
+                for (int k = 0; k < p; ++k) acc -= Wt[(size_t)k * n + i] * dnu[k];
+                yv[i] = acc;
+            }
+            __syncthreads();
+        }
+        lane_ids();
 #pragma unroll
-        for (int s = 0; s < kTiledSlots; ++s) {
-            const int I = s, J = tcol(s);
+        for (int s = 0; s < NS; ++s) {
+            const int I = trow(s), J = tcol(s);
             if (I >= nt || J >= nt) continue;
             if (I > J) continue;
             const int col = 16 * J + c;
@@ -485,7 +590,6 @@ struct TiledFactor {
         }
         __syncthreads();
     }
-
     // out[i] = sum_{k<rows} M[k][i] v[k] for i < cols: the rows are split into
     // NT / cols groups whose partial sums are added in a fixed order.
     __device__ __forceinline__ void colsum(const T *M, int ld, int rows, int cols, const T *v, T *out) {
@@ -543,32 +647,39 @@ struct TiledFactor {
         }
         __syncthreads();
     }
-    __device__ __forceinline__ void gt_mv(const T *v, T *out) { colsum(G, ldg, m, n, v, out); }
+    __device__ __forceinline__ void gt_mv(const T *v, T *out) {
+        if (GL) colsum(G, ldg, m, n, v, out);
+        else colsum(Gsrc, n, m, n, v, out);
+    }
     __device__ __forceinline__ void g_mv(const T *x, T *out) {
         if (GL) {
             rowdot(G, ldg, m, n, x, out);
         } else {
-            mv_rows<T, NT>(G, ldg, m, n, x, out);
+            mv_rows<T, NT>(Gsrc, n, m, n, x, out);
             __syncthreads();
         }
     }
-    // Qs is symmetric: column sums over coalesced rows of the global copy
-    __device__ __forceinline__ void qs_mv(const T *z, T *out) { colsum(Qs, n, n, n, z, out); }
-    __device__ __forceinline__ void finish(const T *D) {
-        lane_ids();
-#pragma unroll
-        for (int s = 0; s < kTiledSlots; ++s) {
-            const int I = s, J = tcol(s);
-            if (I >= nt || J >= nt) continue;
-            if (I > J) continue;
-            const int col = 16 * J + c;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * I + Mfma<T>::row(g, r);
-                if (row <= col && row < n && col < n) Qs[(size_t)row * n + col] = sq[s][r];
-            }
+    // Qs z: column sums over the staged Qs (no equality rows), else
+    // (Q z + Q^T z) / 2 from column sums and row dots over coalesced rows of Q
+    __device__ __forceinline__ void qs_mv(const T *z, T *out) {
+        if constexpr (!EQ) {
+            colsum(Ust, n, n, n, z, out);
+            return;
         }
+        colsum(Q, n, n, n, z, out);
+        mv_rows<T, NT>(Q, n, n, n, z, xv);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) out[i] = T(0.5) * (out[i] + xv[i]);
+        __syncthreads();
+    }
+    __device__ __forceinline__ void finish(const T *D) {
+        store_u();
         for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
+        if constexpr (EQ)
+            for (int e = threadIdx.x; e < p * p; e += NT) {
+                const int i = e / p, j = e - i * p;
+                US[e] = S[i * lds + j];
+            }
         __syncthreads();
     }
 };
