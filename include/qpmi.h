@@ -87,7 +87,8 @@ enum {
     QP_VARIANT_AUTO = 0,
     QP_VARIANT_GENERIC = 1, /* one workgroup per problem, factor in global memory        */
     QP_VARIANT_LDS = 2,     /* one workgroup per problem, factor resident in LDS          */
-    QP_VARIANT_TILED = 3    /* LDS-resident, MFMA-tiled formation/factorization (gfx950)   */
+    QP_VARIANT_TILED = 3,   /* register-resident 16x16 MFMA tiles (nz <= 128; FP32 <= 256) */
+    QP_VARIANT_STREAM = 4   /* factor in the state buffer, 16x16 MFMA tiles streamed       */
 };
 
 /* Problem data of a uniform batch: device pointers plus per-problem strides in

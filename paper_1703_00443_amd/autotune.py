@@ -1,10 +1,11 @@
 """Project-written autotuner: which forward kernel variant each size bucket uses.
 
 A bucket is (dtype, whether the problem has equality rows, nz range).  For each
-bucket the tuner draws a small set of problems from the seeded generator,
-times forward + backward of every candidate variant (tiled MFMA policy where it
-applies, LDS-resident generic, global-memory generic) as one uneven launch and
-keeps the fastest one whose results are all usable.  The table is a JSON file;
+bucket the tuner draws a set of problems from the seeded generator, times
+forward + backward of every candidate variant (register-resident MFMA tiles
+where they apply, streamed MFMA tiles, LDS-resident generic, global-memory
+generic) as one uneven launch and keeps the fastest one whose results are all
+usable.  The table is a JSON file;
 the variant of a problem depends only on its own dims, so results do not depend
 on what else shares a launch.
 
@@ -25,7 +26,7 @@ DEFAULT_TABLE = os.path.join(HERE, "autotune_table.json")
 
 BUCKETS = [(1, 16), (17, 32), (33, 64), (65, 96), (97, 128), (129, 192), (193, 256), (257, 384),
            (385, 512), (513, 1024)]
-VARIANT_NAMES = {0: "auto", 1: "generic", 2: "lds", 3: "tiled"}
+VARIANT_NAMES = {0: "auto", 1: "generic", 2: "lds", 3: "tiled", 4: "stream"}
 
 
 def bucket_of(n: int) -> int:
@@ -60,9 +61,11 @@ class AutotuneTable:
             json.dump(self.data, f, indent=1, sort_keys=True)
 
 
-def candidates(n: int, p: int):
-    c = [1, 2]
-    if p == 0 and n <= 128:
+def candidates(n: int, dtype: str):
+    """Variants that apply to problems of up to n variables: generic, LDS,
+    streamed tiles, and the register-resident tiles (n <= 128; FP32 n <= 256)."""
+    c = [1, 2, 4]
+    if n <= 128 or (dtype == "f32" and n <= 256):
         c.append(3)
     return c
 
@@ -93,7 +96,7 @@ def tune(dtype="f32", samples: int = 24, seed: int = 7, reps: int = 3, buckets=N
             probs = synth.make_varlen(seed * 1000 + bi, dims)
             g = [pr["g"] for pr in probs]
             best = None
-            for v in candidates(max(d[0] for d in dims), 0 if eq == "noeq" else 1):
+            for v in candidates(max(d[0] for d in dims), dk):
                 vb = VarlenBatch(probs, dtype=tdt, variants=[v] * len(probs))
                 dl = vb.pack_vectors(g)
                 vb.forward(); vb.backward(dl)

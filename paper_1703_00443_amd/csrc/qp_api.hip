@@ -74,7 +74,7 @@ int32_t qp_workspace_query(qp_dtype dtype, int32_t batch, qp_dims d, const qp_op
 static int32_t check_opts(const qp_opts *o) {
     if (!o) return QP_EARG;
     if (o->max_iter < 0 || o->max_iter > 100000 || o->refine_steps < 0 || o->refine_steps > 100 ||
-        !(o->tol >= 0.0) || o->flags != 0 || o->variant < 0 || o->variant > QP_VARIANT_TILED)
+        !(o->tol >= 0.0) || o->flags != 0 || o->variant < 0 || o->variant > QP_VARIANT_STREAM)
         return QP_EARG;
     return QP_OK;
 }
@@ -185,7 +185,7 @@ static bool desc_ok(const qp_problem_desc &d) {
     qp_dims dd = {d.nz, d.nineq, d.neq};
     return dims_ok(dd) && d.Q >= 0 && d.q >= 0 && d.A >= 0 && d.b >= 0 && d.G >= 0 && d.h >= 0 &&
            d.z >= 0 && d.lam >= 0 && d.nu >= 0 && d.state >= 0 && d.variant >= 0 &&
-           d.variant <= QP_VARIANT_TILED && (d.state % kAlignBytes) == 0;
+           d.variant <= QP_VARIANT_STREAM && (d.state % kAlignBytes) == 0;
 }
 
 int32_t qp_varlen_workspace_query(qp_dtype dtype, int32_t count, const qp_problem_desc *dh,

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         for (int k = tid; k < m; k += NT) { lam[k] = P.lam[k]; s[k] = P.s[k]; D[k] = Dst[k]; }
         for (int k = tid; k < p; k += NT) { nu[k] = P.nu[k]; r4[k] = T(0); }
         __syncthreads();
-        kkt_solve<T, NT>(U, n, Wt, US, n, p, f, r4, y, tp, tp2, dz, dn);
+        kkt_solve<T, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, dz, dn);
         mv_rows<T, NT>(G, n, m, n, dz, tm);
         __syncthreads();
         for (int k = tid; k < m; k += NT) { ds[k] = -tm[k]; dl[k] = D[k] * tm[k]; }
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
             __syncthreads();
             for (int i = tid; i < n; i += NT) f[i] = r1[i] - f[i];
             __syncthreads();
-            kkt_solve<T, NT>(U, n, Wt, US, n, p, f, r4, y, tp, tp2, ez, en);
+            kkt_solve<T, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, ez, en);
             mv_rows<T, NT>(G, n, m, n, ez, tm);
             __syncthreads();
             for (int k = tid; k < m; k += NT) {

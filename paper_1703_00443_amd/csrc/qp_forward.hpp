@@ -11,7 +11,7 @@
 //
 // Included by one translation unit per element type.
 #pragma once
-#include "qp_policies.hpp"
+#include "qp_stream.hpp"
 
 namespace qpmi {
 
@@ -29,6 +29,14 @@ __host__ __device__ inline int plan_policy(int esz, int n, int m, int p, int var
         } else if (esz == 4 && n <= kTiledBigMaxN) {
             const int gg = TiledLayout<false>(base, n, m, p).end * esz;
             if (gg <= lds_limit) { *lds_bytes = gg; return kPolicyTiledBig; }
+        }
+    }
+    if (variant == QP_VARIANT_AUTO || variant == QP_VARIANT_STREAM) {
+        int kc = 0;
+        bool s_lds = true;
+        if (stream_plan(esz, base, n, m, p, lds_limit, &kc, &s_lds)) {
+            *lds_bytes = StreamLayout(base, n, m, p, kc, s_lds).end * esz;
+            return kPolicyStream;
         }
     }
     if (variant != QP_VARIANT_GENERIC) {
@@ -82,6 +90,9 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunc
         if (pol == kPolicyTiledGLds || pol == kPolicyTiledGGlobal || pol == kPolicyTiledBig) {
             if (P.p > 0) run_tiled<T, true>(pol, P, sm, L);
             else run_tiled<T, false>(pol, P, sm, L);
+        } else if (pol == kPolicyStream) {
+            if (P.p > 0) run_policy<T, StreamFactor<T, true>>(P, sm, L);
+            else run_policy<T, StreamFactor<T, false>>(P, sm, L);
         } else if (pol == kPolicyGenericLds) {
             run_policy<T, GenericFactor<T, kFwdThreads, true>>(P, sm, L);
         } else {
@@ -141,6 +152,9 @@ hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
         if (pol == kPolicyTiledGLds || pol == kPolicyTiledGGlobal || pol == kPolicyTiledBig)
             return L.neq > 0 ? launch_uniform_tiled<T, true>(pol, L, st)
                              : launch_uniform_tiled<T, false>(pol, L, st);
+        if (pol == kPolicyStream)
+            return L.neq > 0 ? launch_uniform<T, StreamFactor<T, true>>(L, st)
+                             : launch_uniform<T, StreamFactor<T, false>>(L, st);
         if (pol == kPolicyGenericLds) return launch_uniform<T, GenericFactor<T, kFwdThreads, true>>(L, st);
         return launch_uniform<T, GenericFactor<T, kFwdThreads, false>>(L, st);
     }

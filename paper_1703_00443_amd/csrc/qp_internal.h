@@ -14,8 +14,13 @@ constexpr int kLdsLimit = 160 * 1024;
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Leading dimension of the stored factor: nz rounded up to whole 16-wide tiles,
+// so that the tile policies can factor in place in the state buffer.
+__host__ __device__ constexpr int u_ld(int n) { return (n + 15) & ~15; }
+
 // Per-problem factor state, in elements of T, each region 256-byte aligned:
-//   U   [nz*nz]      upper triangle (incl. diagonal) = L^{-T}, L L^T = Qs + G^T D G
+//   U   [ldu*ldu]    ldu = u_ld(nz); upper triangle (incl. diagonal) of the
+//                    leading nz x nz block = L^{-T}, L L^T = Qs + G^T D G
 //   D   [nineq]      lambda / s at the returned iterate
 //   Wt  [neq*nz]     Wt = (L^{-1} A^T)^T
 //   US  [neq*neq]    upper triangle = LS^{-T}, LS LS^T = Wt Wt^T (Schur complement)
@@ -26,7 +31,7 @@ struct StateLayout {
 __host__ __device__ inline StateLayout state_layout(int esz, int n, int m, int p) {
     StateLayout s;
     size_t o = 0;
-    s.off_U = o; o += align_up((size_t)n * n * esz, kAlignBytes);
+    s.off_U = o; o += align_up((size_t)u_ld(n) * u_ld(n) * esz, kAlignBytes);
     s.off_D = o; o += align_up((size_t)(m > 0 ? m : 1) * esz, kAlignBytes);
     s.off_Wt = o; o += align_up((size_t)(p > 0 ? p * n : 1) * esz, kAlignBytes);
     s.off_US = o; o += align_up((size_t)(p > 0 ? p * p : 1) * esz, kAlignBytes);
@@ -85,7 +90,7 @@ struct BwdLaunch {
 // requested variant and the device LDS limit, so a problem is solved with the
 // same arithmetic alone or inside any batch.
 enum { kPolicyGenericGlobal = 0, kPolicyGenericLds = 1, kPolicyTiledGGlobal = 2, kPolicyTiledGLds = 3,
-       kPolicyTiledBig = 4, kPolicyNone = -1 };
+       kPolicyTiledBig = 4, kPolicyStream = 5, kPolicyNone = -1 };
 int fwd_plan(int esz, int n, int m, int p, int variant, int lds_limit, int *lds_bytes);
 
 // Workgroups of the forward kernel that fit on the device at once with this LDS.

@@ -95,7 +95,7 @@ struct GenericFactor {
         const GenericLayout<HL> L(base, n, m, p);
         xd = sm + L.xd; xdp = sm + L.xdp; y = sm + L.y; t1 = sm + L.t1; t2 = sm + L.t2;
         tq = sm + L.tq;
-        if (HL) { H = sm + L.H; ldh = h_ld(n); } else { H = U_state; ldh = n; }
+        if (HL) { H = sm + L.H; ldh = h_ld(n); } else { H = U_state; ldh = u_ld(n); }
     }
     __device__ __forceinline__ void prepare() {}
     __device__ __forceinline__ bool factor(const T *D) {
@@ -126,7 +126,7 @@ struct GenericFactor {
         if (HL)
             for (int e = threadIdx.x; e < n * n; e += NT) {
                 const int i = e / n, j = e - i * n;
-                U_state[e] = H[(size_t)i * ldh + j];
+                U_state[(size_t)i * u_ld(n) + j] = H[(size_t)i * ldh + j];
             }
         for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
         __syncthreads();
@@ -172,6 +172,76 @@ struct Mfma<float> {
 
 
 
+// out[i] = sum_{k<rows} M[k][i] v[k] for i < cols.  When cols < NT the rows
+// are split into up to eight groups whose partial sums (scratch, NT entries)
+// are added in a fixed order; otherwise one thread per column.
+template <typename T, int NT>
+__device__ __forceinline__ void colsum_split(const T *M, int ld, int rows, int cols, const T *v, T *out,
+                                             T *scratch) {
+    const int ng = cols > 0 ? max(1, min(NT / cols, 8)) : 1;
+    const int chunk = (rows + ng - 1) / ng;
+    for (int t = threadIdx.x; t < ng * cols; t += NT) {
+        const int q = t / cols, i = t - q * cols;
+        const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int k = k0;
+        for (; k + 3 < k1; k += 4) {
+            a0 += M[(size_t)k * ld + i] * v[k];
+            a1 += M[(size_t)(k + 1) * ld + i] * v[k + 1];
+            a2 += M[(size_t)(k + 2) * ld + i] * v[k + 2];
+            a3 += M[(size_t)(k + 3) * ld + i] * v[k + 3];
+        }
+        for (; k < k1; ++k) a0 += M[(size_t)k * ld + i] * v[k];
+        const T r = (a0 + a1) + (a2 + a3);
+        if (ng == 1) out[i] = r;
+        else scratch[t] = r;
+    }
+    if (ng > 1) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < cols; i += NT) {
+            T acc = scratch[i];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * cols + i];
+            out[i] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// out[k] = sum_{i<cols} M[k][i] x[i] for k < rows (M in LDS, odd ld): the
+// columns are split into up to eight groups when rows < NT.
+template <typename T, int NT>
+__device__ __forceinline__ void rowdot_split(const T *M, int ld, int rows, int cols, const T *x, T *out,
+                                             T *scratch) {
+    const int ng = rows > 0 ? max(1, min(NT / rows, 8)) : 1;
+    const int chunk = (cols + ng - 1) / ng;
+    for (int t = threadIdx.x; t < ng * rows; t += NT) {
+        const int q = t / rows, k = t - q * rows;
+        const int i0 = q * chunk, i1 = min(cols, i0 + chunk);
+        const T *row = M + (size_t)k * ld;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int i = i0;
+        for (; i + 3 < i1; i += 4) {
+            a0 += row[i] * x[i];
+            a1 += row[i + 1] * x[i + 1];
+            a2 += row[i + 2] * x[i + 2];
+            a3 += row[i + 3] * x[i + 3];
+        }
+        for (; i < i1; ++i) a0 += row[i] * x[i];
+        const T r = (a0 + a1) + (a2 + a3);
+        if (ng == 1) out[k] = r;
+        else scratch[t] = r;
+    }
+    if (ng > 1) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < rows; k += NT) {
+            T acc = scratch[k];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * rows + k];
+            out[k] = acc;
+        }
+    }
+    __syncthreads();
+}
+
 // Which tiles a wavefront holds (see the grid comment above).
 template <int NTL>
 struct TileMap {
@@ -189,7 +259,7 @@ struct TiledFactor {
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr int NS = TileMap<NTL>::NS;
     using v4 = typename Mfma<T>::v4;
-    int n, m, p, nt, np, pt, ldg, lds;
+    int n, m, p, nt, np, pt, ldg, lds, ldu;
     const T *Q, *Gsrc, *A;
     const T *G;  // LDS copy (GL) or the staging chunk
     T *Ust, *Dst, *Wt, *US;  // state: U (row-major, ld n), D, Wt (p x n), US (p x p)
@@ -220,7 +290,7 @@ struct TiledFactor {
         panel = sm + L.panel; scratch = sm + L.scratch; dbuf = sm + L.dbuf;
         S = sm + L.S; xdp = sm + L.xdp; pv1 = sm + L.pv1; pv2 = sm + L.pv2;
         flag = reinterpret_cast<int *>(sm + L.flag);
-        G = sm + L.G; ldg = np + 1; lds = h_ld(p);
+        G = sm + L.G; ldg = np + 1; lds = h_ld(p); ldu = u_ld(n);
         lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
     }
 
@@ -236,8 +306,8 @@ struct TiledFactor {
     }
 
     // Without equality rows the U region of the state is free until finish():
-    // it holds Qs = (Q + Q^T) / 2 for coalesced single loads in form() and
-    // qs_mv().  With equality rows the Schur step stores U there every
+    // it holds Qs = (Q + Q^T) / 2 (row-major, ld nz) for coalesced single
+    // loads in form() and qs_mv().  With equality rows the Schur step stores U there every
     // factorization, and Qs is taken from Q itself.
     __device__ __forceinline__ void prepare() {
         if (!EQ)
@@ -449,7 +519,7 @@ struct TiledFactor {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * I + Mfma<T>::row(g, r);
-                if (row <= col && row < n && col < n) Ust[(size_t)row * n + col] = sq[s][r];
+                if (row <= col && row < n && col < n) Ust[(size_t)row * ldu + col] = sq[s][r];
             }
         }
     }
@@ -470,7 +540,7 @@ struct TiledFactor {
                 const int k = kb + g;
                 const bool ka = arow < p && k < n, kbv = k < n && col < n && k <= col;
                 const T av = A[ka ? (size_t)arow * n + k : 0];
-                const T bv = Ust[kbv ? (size_t)k * n + col : 0];
+                const T bv = Ust[kbv ? (size_t)k * ldu + col : 0];
                 d = Mfma<T>::mma(ka ? av : T(0), kbv ? bv : T(0), d);
             }
 #pragma unroll
@@ -590,62 +660,11 @@ struct TiledFactor {
         }
         __syncthreads();
     }
-    // out[i] = sum_{k<rows} M[k][i] v[k] for i < cols: the rows are split into
-    // NT / cols groups whose partial sums are added in a fixed order.
     __device__ __forceinline__ void colsum(const T *M, int ld, int rows, int cols, const T *v, T *out) {
-        const int ng = cols > 0 ? max(1, min(NT / cols, 8)) : 1;
-        const int chunk = (rows + ng - 1) / ng;
-        const int t = threadIdx.x;
-        if (t < ng * cols) {
-            const int q = t / cols, i = t - q * cols;
-            const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
-            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            int k = k0;
-            for (; k + 3 < k1; k += 4) {
-                a0 += M[(size_t)k * ld + i] * v[k];
-                a1 += M[(size_t)(k + 1) * ld + i] * v[k + 1];
-                a2 += M[(size_t)(k + 2) * ld + i] * v[k + 2];
-                a3 += M[(size_t)(k + 3) * ld + i] * v[k + 3];
-            }
-            for (; k < k1; ++k) a0 += M[(size_t)k * ld + i] * v[k];
-            scratch[q * cols + i] = (a0 + a1) + (a2 + a3);
-        }
-        __syncthreads();
-        for (int i = t; i < cols; i += NT) {
-            T acc = scratch[i];
-            for (int q = 1; q < ng; ++q) acc += scratch[q * cols + i];
-            out[i] = acc;
-        }
-        __syncthreads();
+        colsum_split<T, NT>(M, ld, rows, cols, v, out, scratch);
     }
-    // out[k] = sum_{i<cols} M[k][i] x[i] for k < rows (LDS-resident M, odd ld):
-    // the columns are split into NT / rows groups.
     __device__ __forceinline__ void rowdot(const T *M, int ld, int rows, int cols, const T *x, T *out) {
-        const int ng = rows > 0 ? max(1, min(NT / rows, 8)) : 1;
-        const int chunk = (cols + ng - 1) / ng;
-        const int t = threadIdx.x;
-        if (t < ng * rows) {
-            const int q = t / rows, k = t - q * rows;
-            const int i0 = q * chunk, i1 = min(cols, i0 + chunk);
-            const T *row = M + (size_t)k * ld;
-            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            int i = i0;
-            for (; i + 3 < i1; i += 4) {
-                a0 += row[i] * x[i];
-                a1 += row[i + 1] * x[i + 1];
-                a2 += row[i + 2] * x[i + 2];
-                a3 += row[i + 3] * x[i + 3];
-            }
-            for (; i < i1; ++i) a0 += row[i] * x[i];
-            scratch[q * rows + k] = (a0 + a1) + (a2 + a3);
-        }
-        __syncthreads();
-        for (int k = t; k < rows; k += NT) {
-            T acc = scratch[k];
-            for (int q = 1; q < ng; ++q) acc += scratch[q * rows + k];
-            out[k] = acc;
-        }
-        __syncthreads();
+        rowdot_split<T, NT>(M, ld, rows, cols, x, out, scratch);
     }
     __device__ __forceinline__ void gt_mv(const T *v, T *out) {
         if (GL) colsum(G, ldg, m, n, v, out);

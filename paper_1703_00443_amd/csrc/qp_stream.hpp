@@ -1,0 +1,411 @@
+// Streamed-tile factorization policy for problems whose factor does not fit
+// in registers or LDS: the padded square of 16x16 tiles is factored in place
+// in the U region of the state buffer (ld u_ld(nz)), and the tiles stream
+// through the registers of the eight wavefronts for each MFMA update.
+//
+//   form:  H = Qs + G^T D G, lower tiles, GT output tiles per wavefront and
+//          pass held in MFMA accumulators; G streamed through LDS in chunks
+//          of kc rows (each pass reads G once); upper tiles zeroed.
+//   chol:  the fused Cholesky + inverse of the tiled policy, by 16-column
+//          panels: column P of the square to LDS, the diagonal tile's 16
+//          steps in one wavefront, panel tiles times X_PP^T, then the
+//          rank-16 update of every tile right of the panel (loaded from the
+//          state, four MFMAs, stored back), four tiles in flight per wavefront.
+//   solve: triangular matrix-vector products over the stored U.
+//   Schur complement on A (equality rows): as in the tiled policy.
+#pragma once
+#include "qp_policies.hpp"
+
+namespace qpmi {
+
+// s_lds: the Schur block S sits in LDS (sharing the staging buffer); otherwise
+// it is factored in place in the US region of the state.
+struct StreamLayout {
+    int yv, xv, panel, scratch, dbuf, flag, xdp, pv1, pv2, buf, end;
+    __host__ __device__ StreamLayout(int base, int n, int m, int p, int kc, bool s_lds) {
+        (void)m;
+        const int nt = (n + 15) / 16, np = 16 * nt;
+        int o = base;
+        yv = o; o += np; xv = o; o += np;
+        panel = o; o += np * 17;
+        scratch = o; o += 64 * kTiledWaves;
+        dbuf = o; o += 16;
+        flag = o; o += 4;
+        xdp = o; o += pad4(p); pv1 = o; o += pad4(p); pv2 = o; o += pad4(p);
+        o = (o + 15) & ~15;
+        buf = o;  // G staging chunk, then the Schur block S (ld p | 1)
+        const int gsz = kc * (np + 1), ssz = (p > 0 && s_lds) ? p * h_ld(p) : 0;
+        end = o + (gsz > ssz ? gsz : ssz);
+    }
+};
+
+// Plan of the policy: rows of G per staging chunk (the largest of 64, 32, ...,
+// 4 that fits), with S in LDS if any chunk size fits that way, else with S in
+// the state.  Returns false when nothing fits.
+__host__ __device__ inline bool stream_plan(int esz, int base, int n, int m, int p, int lds_limit, int *kc,
+                                            bool *s_lds) {
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool sl = pass == 0;
+        if (!sl && p == 0) break;
+        for (int k = 64; k >= 4; k >>= 1)
+            if (StreamLayout(base, n, m, p, k, sl).end * esz <= lds_limit) {
+                *kc = k;
+                *s_lds = sl;
+                return true;
+            }
+    }
+    return false;
+}
+
+template <typename T, bool EQ>
+struct StreamFactor {
+    static constexpr int NT = 64 * kTiledWaves;
+    static constexpr int GT = 8;  // form(): tiles per wavefront and pass
+    using v4 = typename Mfma<T>::v4;
+    int n, m, p, nt, np, pt, ldg, lds, ldu, kc;
+    bool s_lds;
+    const T *Q, *Gsrc, *A;
+    T *U, *Dst, *Wt, *US;
+    T *yv, *xv, *panel, *scratch, *dbuf, *xdp, *pv1, *pv2, *gbuf, *S;
+    int *flag;
+    int w, lane, g, c;
+
+    __device__ __forceinline__ void lane_ids() {
+        const int t = opaque_tid();
+        lane = t & 63; g = lane >> 4; c = lane & 15;
+        w = __builtin_amdgcn_readfirstlane(t >> 6);
+    }
+
+    __device__ StreamFactor(const Prob<T> &P, T *sm, int base) {
+        n = P.n; m = P.m; p = P.p;
+        nt = (n + 15) / 16; np = 16 * nt; pt = (p + 15) / 16;
+        Q = P.Q; Gsrc = P.G; A = P.A;
+        const StateLayout SL = state_layout(sizeof(T), n, m, p);
+        U = (T *)(P.state + SL.off_U);
+        Dst = (T *)(P.state + SL.off_D);
+        Wt = (T *)(P.state + SL.off_Wt);
+        US = (T *)(P.state + SL.off_US);
+        kc = 4; s_lds = true;
+        (void)stream_plan(sizeof(T), base, n, m, p, P.lds_limit, &kc, &s_lds);
+        const StreamLayout L(base, n, m, p, kc, s_lds);
+        yv = sm + L.yv; xv = sm + L.xv; panel = sm + L.panel; scratch = sm + L.scratch;
+        dbuf = sm + L.dbuf; flag = reinterpret_cast<int *>(sm + L.flag);
+        xdp = sm + L.xdp; pv1 = sm + L.pv1; pv2 = sm + L.pv2;
+        gbuf = sm + L.buf;
+        ldg = np + 1; ldu = u_ld(n);
+        if (s_lds) { S = sm + L.buf; lds = h_ld(p); } else { S = US; lds = p; }
+        lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
+    }
+
+    __device__ __forceinline__ void prepare() {}
+
+    // Lower tile t (row-major order over the lower triangle of the tile grid).
+    __device__ __forceinline__ static void lower_tile(int t, int &I, int &J) {
+        int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        while (i * (i + 1) / 2 > t) --i;
+        I = i;
+        J = t - i * (i + 1) / 2;
+    }
+
+    __device__ __forceinline__ void form(const T *D) {
+        lane_ids();
+        // upper tiles start at zero (they become X^T = L^{-T} strictly above the diagonal)
+        for (int t = w; t < nt * nt; t += kTiledWaves) {
+            const int I = t / nt, J = t - I * nt;
+            if (I >= J) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) U[(size_t)(16 * I + Mfma<T>::row(g, r)) * ldu + 16 * J + c] = T(0);
+        }
+        const int NL = nt * (nt + 1) / 2;
+        for (int t0 = 0; t0 < NL; t0 += kTiledWaves * GT) {
+            int ti[GT], tj[GT];
+            v4 acc[GT];
+#pragma unroll
+            for (int j = 0; j < GT; ++j) {
+                const int t = t0 + w * GT + j;
+                int I = -1, J = 0;
+                if (t < NL) lower_tile(t, I, J);
+                ti[j] = I; tj[j] = J;
+                v4 a = {0, 0, 0, 0};
+                if (I >= 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * I + Mfma<T>::row(g, r), col = 16 * J + c;
+                        const bool in = row < n && col < n;
+                        const T qa = Q[in ? (size_t)row * n + col : 0];
+                        const T qb = Q[in ? (size_t)col * n + row : 0];
+                        a[r] = in ? T(0.5) * (qa + qb) : (row == col ? T(1) : T(0));
+                    }
+                }
+                acc[j] = a;
+            }
+            for (int k0 = 0; k0 < m; k0 += kc) {
+                const int rows = min(kc, m - k0), rp = (rows + 3) & ~3;
+                __syncthreads();  // previous chunk consumed
+                for (int e = threadIdx.x; e < rp * np; e += NT) {
+                    const int k = e / np, i = e - k * np;
+                    gbuf[k * ldg + i] = (k < rows && i < n) ? Gsrc[(size_t)(k0 + k) * n + i] : T(0);
+                }
+                __syncthreads();
+                lane_ids();
+                for (int kb = 0; kb < rows; kb += 4) {
+                    const int k = kb + g;
+                    const T *Gk = gbuf + k * ldg;
+                    const int kg = k0 + k;
+                    const T dk = D[kg < m ? kg : m - 1] * T(kg < m ? 1 : 0);
+#pragma unroll
+                    for (int j = 0; j < GT; ++j) {
+                        if (ti[j] < 0) continue;
+                        acc[j] = Mfma<T>::mma(Gk[16 * ti[j] + c], dk * Gk[16 * tj[j] + c], acc[j]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < GT; ++j) {
+                if (ti[j] < 0) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * ti[j] + Mfma<T>::row(g, r), col = 16 * tj[j] + c;
+                    U[(size_t)row * ldu + col] = (ti[j] == tj[j] && row < col) ? T(0) : acc[j][r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Trailing tile u of panel P: columns C > P, rows R <= P or R >= C, in
+    // column-major order of that set.
+    __device__ __forceinline__ void trail_tile(int P, int u, int &R, int &C) const {
+        int cc = P + 1, cnt = P + 1 + nt - cc;
+        while (u >= cnt) { u -= cnt; ++cc; cnt = P + 1 + nt - cc; }
+        C = cc;
+        R = (u <= P) ? u : cc + (u - (P + 1));
+    }
+
+    __device__ __forceinline__ bool chol_inv() {
+        if (threadIdx.x == 0) *flag = 0;
+        for (int P = 0; P < nt; ++P) {
+            // ---- (1a) column P of the square to the LDS panel, ld 17
+            for (int e = threadIdx.x; e < np * 16; e += NT) {
+                const int row = e >> 4, col = e & 15;
+                panel[row * 17 + col] = U[(size_t)row * ldu + 16 * P + col];
+            }
+            __syncthreads();
+            lane_ids();
+            // ---- (1b) the diagonal tile, 16 dependent steps in one wavefront
+            if (w == (P & 7)) {
+                int rl[4];
+                v4 t;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    rl[r] = Mfma<T>::row(g, r);
+                    t[r] = panel[(16 * P + rl[r]) * 17 + c];
+                }
+                bool bad = false;
+                for (int kk = 0; kk < 16; ++kk) {
+                    if (c == kk) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) dbuf[rl[r]] = t[r];
+                    }
+                    // wave-local LDS exchange: wait for the stores before the loads
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __builtin_amdgcn_wave_barrier();
+                    const T vk = dbuf[kk];
+                    const T vc = dbuf[c];
+                    T vr[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) vr[r] = dbuf[rl[r]];
+                    bad |= !(vk > T(0)) || !isfinite(vk);
+                    const T inv = Mfma<T>::rsqrt(vk);
+                    const T wc = vc * (inv * inv);
+                    const bool upd_c = c > kk, fin_c = c == kk;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rl[r];
+                        const T v = (row == kk) ? T(1) : vr[r];
+                        const bool upd = upd_c && (row >= c || row <= kk);
+                        const T xu = upd ? t[r] - v * wc : t[r];
+                        t[r] = fin_c ? v * inv : xu;
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __builtin_amdgcn_wave_barrier();
+                }
+                if (bad && c == 0 && g == 0) *flag = 1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    panel[(16 * P + rl[r]) * 17 + c] = t[r];
+                    U[(size_t)(16 * P + rl[r]) * ldu + 16 * P + c] = t[r];
+                }
+            }
+            __syncthreads();
+            if (*flag) return false;
+            // ---- (2) panel tiles R != P:  tile <- tile * X_PP^T
+            lane_ids();
+            for (int R = w; R < nt; R += kTiledWaves) {
+                if (R == P) continue;
+                v4 d = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kq = 4 * q + g;
+                    const T a = panel[(16 * R + c) * 17 + kq];
+                    const T bx = panel[(16 * P + kq) * 17 + c];
+                    d = Mfma<T>::mma(a, (kq <= c) ? bx : T(0), d);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * R + Mfma<T>::row(g, r);
+                    panel[row * 17 + c] = d[r];
+                    U[(size_t)row * ldu + 16 * P + c] = d[r];
+                }
+            }
+            __syncthreads();
+            if (P + 1 == nt) break;
+            // ---- (3) rank-16 update of the tiles right of the panel
+            const int cols = nt - P - 1;
+            const int total = cols * (P + 1) + cols * (cols + 1) / 2;
+            lane_ids();
+            for (int u0 = w; u0 < total; u0 += 4 * kTiledWaves) {
+                int R[4], C[4];
+                v4 tl[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int u = u0 + b * kTiledWaves;
+                    R[b] = -1; C[b] = 0;
+                    if (u < total) trail_tile(P, u, R[b], C[b]);
+                    v4 x = {0, 0, 0, 0};
+                    if (R[b] >= 0) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            x[r] = U[(size_t)(16 * R[b] + Mfma<T>::row(g, r)) * ldu + 16 * C[b] + c];
+                    }
+                    tl[b] = x;
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (R[b] < 0) continue;
+                    v4 d = {0, 0, 0, 0};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int kq = 4 * q + g;
+                        T a = panel[(16 * R[b] + c) * 17 + kq];
+                        if (R[b] == P) a = (kq >= c) ? a : T(0);  // X rows of the panel: steps k >= r only
+                        const T bb = panel[(16 * C[b] + c) * 17 + kq];
+                        d = Mfma<T>::mma(a, bb, d);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * R[b] + Mfma<T>::row(g, r), col = 16 * C[b] + c;
+                        const bool keep = !(R[b] == C[b] && row < col);  // X part of a diagonal tile
+                        U[(size_t)row * ldu + col] = tl[b][r] - (keep ? d[r] : T(0));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ bool schur() {
+        lane_ids();
+        for (int t = w; t < pt * nt; t += kTiledWaves) {
+            const int K = t / nt, J = t - K * nt;
+            const int arow = 16 * K + c, col = 16 * J + c;
+            const int kend = min(n, 16 * J + 16);
+            v4 d = {0, 0, 0, 0};
+            for (int kb = 0; kb < kend; kb += 4) {
+                const int k = kb + g;
+                const bool ka = arow < p && k < n, kbv = k < n && col < n && k <= col;
+                const T av = A[ka ? (size_t)arow * n + k : 0];
+                const T bv = U[kbv ? (size_t)k * ldu + col : 0];
+                d = Mfma<T>::mma(ka ? av : T(0), kbv ? bv : T(0), d);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * K + Mfma<T>::row(g, r);
+                if (row < p && col < n) Wt[(size_t)row * n + col] = d[r];
+            }
+        }
+        __syncthreads();
+        lane_ids();
+        for (int t = w; t < pt * pt; t += kTiledWaves) {
+            const int K = t / pt, Lb = t - K * pt;
+            const int ra = 16 * K + c, rb = 16 * Lb + c;
+            v4 d = {0, 0, 0, 0};
+            if (Lb <= K) {
+                for (int kb = 0; kb < n; kb += 4) {
+                    const int k = kb + g;
+                    const bool va = ra < p && k < n, vb = rb < p && k < n;
+                    const T av = Wt[va ? (size_t)ra * n + k : 0];
+                    const T bv = Wt[vb ? (size_t)rb * n + k : 0];
+                    d = Mfma<T>::mma(va ? av : T(0), vb ? bv : T(0), d);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * K + Mfma<T>::row(g, r), col = 16 * Lb + c;
+                if (row < p && col < p) S[row * lds + col] = (col <= row) ? d[r] : T(0);
+            }
+        }
+        __syncthreads();
+        return ::qpmi::chol_inv<T, NT>(S, lds, p, xdp);
+    }
+
+    __device__ __forceinline__ bool factor(const T *D) {
+        form(D);
+        if (!chol_inv()) return false;
+        if constexpr (EQ) return schur();
+        return true;
+    }
+
+    // y = U^T f;  (equality rows) dnu = US US^T (Wt y - r4), y -= Wt^T dnu;  dz = U y
+    __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
+        ut_mv<T, NT>(U, ldu, n, f, yv);
+        __syncthreads();
+        if constexpr (EQ) {
+            mv_rows<T, NT>(Wt, n, p, n, yv, pv1);
+            __syncthreads();
+            for (int k = threadIdx.x; k < p; k += NT) pv1[k] -= r4[k];
+            __syncthreads();
+            ut_mv<T, NT>(S, lds, p, pv1, pv2);
+            __syncthreads();
+            u_mv<T, NT>(S, lds, p, pv2, dnu);
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += NT) {
+                T acc = yv[i];
+                for (int k = 0; k < p; ++k) acc -= Wt[(size_t)k * n + i] * dnu[k];
+                yv[i] = acc;
+            }
+            __syncthreads();
+        }
+        u_mv<T, NT>(U, ldu, n, yv, dz);
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void gt_mv(const T *v, T *out) {
+        colsum_split<T, NT>(Gsrc, n, m, n, v, out, scratch);
+    }
+    __device__ __forceinline__ void g_mv(const T *x, T *out) {
+        mv_rows<T, NT>(Gsrc, n, m, n, x, out);
+        __syncthreads();
+    }
+    __device__ __forceinline__ void qs_mv(const T *z, T *out) {
+        colsum_split<T, NT>(Q, n, n, n, z, out, scratch);
+        mv_rows<T, NT>(Q, n, n, n, z, xv);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) out[i] = T(0.5) * (out[i] + xv[i]);
+        __syncthreads();
+    }
+    __device__ __forceinline__ void finish(const T *D) {
+        for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
+        if constexpr (EQ)
+            if (s_lds)
+                for (int e = threadIdx.x; e < p * p; e += NT) {
+                    const int i = e / p, j = e - i * p;
+                    US[e] = S[i * lds + j];
+                }
+        __syncthreads();
+    }
+};
+
+}  // namespace qpmi

@@ -194,3 +194,21 @@ def test_big_tiles_fp32(dims, B):
     b = synth.make_batch(seed=4096 + n, B=B, n=n, m=m, p=p, row_normalize=True)
     out = _run(b, np.float32, opts_over={"variant": qb.VARIANT_TILED})
     _check(b, out, np.float32, range(B))
+
+
+@pytest.mark.parametrize("dims,dtypes", [
+    ((1, 3, 0), "both"), ((16, 16, 0), "both"), ((17, 40, 3), "both"), ((100, 100, 0), "both"),
+    ((130, 260, 10), "both"), ((200, 200, 50), "both"), ((300, 300, 20), "f32"),
+    ((512, 600, 64), "f32"), ((200, 200, 150), "both"), ((256, 256, 200), "f32")])
+def test_stream_policy(dims, dtypes):
+    """The streamed-tile policy (factor in the state buffer, 16x16 MFMA tiles
+    streamed through registers, G staged through LDS): tile edges, equality
+    rows, sizes beyond the register-resident policies, and Schur blocks too
+    large for LDS (factored in the state: FP64 at neq=150, FP32 at neq=200)."""
+    from paper_1703_00443_amd import binding as qb
+    n, m, p = dims
+    B = 1 if n >= 300 else 2
+    b = synth.make_batch(seed=8080 + n, B=B, n=n, m=m, p=p, row_normalize=True)
+    for dtype in ((np.float64, np.float32) if dtypes == "both" else (np.float32,)):
+        out = _run(b, dtype, opts_over={"variant": qb.VARIANT_STREAM})
+        _check(b, out, dtype, range(B), need_grad=dtype == np.float64 or m >= n)
