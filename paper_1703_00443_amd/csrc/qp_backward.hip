@@ -72,6 +72,7 @@ struct BwdLayout {
     int z, g, dz, f, y, tn, tn2, r1, ez;              // n
     int lam, s, D, dl, ds, r2, r3, tm, el, es, tm2;   // m
     int nu, dn, r4, tp, tp2, en;                      // p
+    int scr;                                          // partial sums of the split products
     int red, end;
     __host__ __device__ BwdLayout(int n, int m, int p) {
         const int N = pad4(n), M = pad4(m), Pp = pad4(p);
@@ -83,6 +84,7 @@ struct BwdLayout {
         tm2 = o; o += M;
         nu = o; o += Pp; dn = o; o += Pp; r4 = o; o += Pp; tp = o; o += Pp; tp2 = o; o += Pp;
         en = o; o += Pp;
+        scr = o; o += 512;
         red = o; o += 64;
         end = o;
     }
@@ -114,13 +116,13 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
           *r2 = sm + Lo.r2, *r3 = sm + Lo.r3, *tm = sm + Lo.tm, *el = sm + Lo.el, *es = sm + Lo.es,
           *tm2 = sm + Lo.tm2;
         T *nu = sm + Lo.nu, *dn = sm + Lo.dn, *r4 = sm + Lo.r4, *tp = sm + Lo.tp,
-          *tp2 = sm + Lo.tp2, *en = sm + Lo.en;
+          *tp2 = sm + Lo.tp2, *en = sm + Lo.en, *scr = sm + Lo.scr;
 
         for (int i = tid; i < n; i += NT) { z[i] = P.z[i]; g[i] = P.g[i]; f[i] = -P.g[i]; }
         for (int k = tid; k < m; k += NT) { lam[k] = P.lam[k]; s[k] = P.s[k]; D[k] = Dst[k]; }
         for (int k = tid; k < p; k += NT) { nu[k] = P.nu[k]; r4[k] = T(0); }
         __syncthreads();
-        kkt_solve<T, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, dz, dn);
+        kkt_solve<T, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, dz, dn, scr);
         mv_rows<T, NT>(G, n, m, n, dz, tm);
         __syncthreads();
         for (int k = tid; k < m; k += NT) { ds[k] = -tm[k]; dl[k] = D[k] * tm[k]; }
@@ -129,14 +131,11 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         for (int r = 0; r < L.refine_steps; ++r) {
             // residual of K_sym [dz; ds; dl; dn] = [-g; 0; 0; 0]
             mv_rows<T, NT>(Q, n, n, n, dz, tn);
-            mv_cols<T, NT>(Q, n, n, n, dz, tn2);
-            mv_cols<T, NT>(G, n, m, n, dl, r1);
             mv_rows<T, NT>(G, n, m, n, dz, tm);
-            if (p > 0) {
-                mv_cols<T, NT>(A, n, p, n, dn, y);
-                mv_rows<T, NT>(A, n, p, n, dz, tp);
-            }
-            __syncthreads();
+            if (p > 0) mv_rows<T, NT>(A, n, p, n, dz, tp);
+            colsum_split<T, NT>(Q, n, n, n, dz, tn2, scr);
+            colsum_split<T, NT>(G, n, m, n, dl, r1, scr);
+            if (p > 0) colsum_split<T, NT>(A, n, p, n, dn, y, scr);
             for (int i = tid; i < n; i += NT) {
                 T acc = T(0.5) * (tn[i] + tn2[i]) + r1[i];
                 if (p > 0) acc += y[i];
@@ -152,11 +151,10 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
             for (int k = tid; k < p; k += NT) r4[k] = -tp[k];
             __syncthreads();
             // correction: f = r1 - G^T (r2 - D r3)
-            mv_cols<T, NT>(G, n, m, n, tm2, f);
-            __syncthreads();
+            colsum_split<T, NT>(G, n, m, n, tm2, f, scr);
             for (int i = tid; i < n; i += NT) f[i] = r1[i] - f[i];
             __syncthreads();
-            kkt_solve<T, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, ez, en);
+            kkt_solve<T, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, ez, en, scr);
             mv_rows<T, NT>(G, n, m, n, ez, tm);
             __syncthreads();
             for (int k = tid; k < m; k += NT) {
@@ -219,7 +217,7 @@ __global__ __launch_bounds__(NT) void qp_grad_assemble_kernel(BwdLaunch L) {
     }
 }
 
-constexpr int kBwdThreads = 256;
+constexpr int kBwdThreads = 512;
 
 template <typename T>
 static hipError_t launch_bwd_t(const BwdLaunch &L, hipStream_t st, int max_rows) {

@@ -101,6 +101,111 @@ __device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int row
     }
 }
 
+// out[i] = sum_{k<rows} M[k][i] v[k] for i < cols.  When cols < NT the rows
+// are split into up to eight groups whose partial sums (scratch, NT entries)
+// are added in a fixed order; otherwise one thread per column.
+template <typename T, int NT>
+__device__ __forceinline__ void colsum_split(const T *M, int ld, int rows, int cols, const T *v, T *out,
+                                             T *scratch) {
+    const int ng = cols > 0 ? max(1, min(NT / cols, 8)) : 1;
+    const int chunk = (rows + ng - 1) / ng;
+    for (int t = threadIdx.x; t < ng * cols; t += NT) {
+        const int q = t / cols, i = t - q * cols;
+        const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int k = k0;
+        for (; k + 3 < k1; k += 4) {
+            a0 += M[(size_t)k * ld + i] * v[k];
+            a1 += M[(size_t)(k + 1) * ld + i] * v[k + 1];
+            a2 += M[(size_t)(k + 2) * ld + i] * v[k + 2];
+            a3 += M[(size_t)(k + 3) * ld + i] * v[k + 3];
+        }
+        for (; k < k1; ++k) a0 += M[(size_t)k * ld + i] * v[k];
+        const T r = (a0 + a1) + (a2 + a3);
+        if (ng == 1) out[i] = r;
+        else scratch[t] = r;
+    }
+    if (ng > 1) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < cols; i += NT) {
+            T acc = scratch[i];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * cols + i];
+            out[i] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// out[k] = sum_{i<cols} M[k][i] x[i] for k < rows (M in LDS, odd ld): the
+// columns are split into up to eight groups when rows < NT.
+template <typename T, int NT>
+__device__ __forceinline__ void rowdot_split(const T *M, int ld, int rows, int cols, const T *x, T *out,
+                                             T *scratch) {
+    const int ng = rows > 0 ? max(1, min(NT / rows, 8)) : 1;
+    const int chunk = (cols + ng - 1) / ng;
+    for (int t = threadIdx.x; t < ng * rows; t += NT) {
+        const int q = t / rows, k = t - q * rows;
+        const int i0 = q * chunk, i1 = min(cols, i0 + chunk);
+        const T *row = M + (size_t)k * ld;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int i = i0;
+        for (; i + 3 < i1; i += 4) {
+            a0 += row[i] * x[i];
+            a1 += row[i + 1] * x[i + 1];
+            a2 += row[i + 2] * x[i + 2];
+            a3 += row[i + 3] * x[i + 3];
+        }
+        for (; i < i1; ++i) a0 += row[i] * x[i];
+        const T r = (a0 + a1) + (a2 + a3);
+        if (ng == 1) out[k] = r;
+        else scratch[t] = r;
+    }
+    if (ng > 1) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < rows; k += NT) {
+            T acc = scratch[k];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * rows + k];
+            out[k] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// y[i] = sum_{j<=i} U[j][i] f[j] for i < n (U upper triangular, incl. the
+// diagonal): the rows are split into up to eight groups when n < NT, partial
+// sums (scratch, NT entries) added in a fixed order; four loads in flight per
+// thread.  Ends with a workgroup barrier.
+template <typename T, int NT>
+__device__ __forceinline__ void ut_mv_split(const T *U, int ld, int n, const T *f, T *y, T *scratch) {
+    const int ng = n > 0 ? max(1, min(NT / n, 8)) : 1;
+    const int chunk = (n + ng - 1) / ng;
+    for (int t = threadIdx.x; t < ng * n; t += NT) {
+        const int q = t / n, i = t - q * n;
+        const int j0 = q * chunk, j1 = min(i + 1, j0 + chunk);
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int j = j0;
+        for (; j + 3 < j1; j += 4) {
+            a0 += U[(size_t)j * ld + i] * f[j];
+            a1 += U[(size_t)(j + 1) * ld + i] * f[j + 1];
+            a2 += U[(size_t)(j + 2) * ld + i] * f[j + 2];
+            a3 += U[(size_t)(j + 3) * ld + i] * f[j + 3];
+        }
+        for (; j < j1; ++j) a0 += U[(size_t)j * ld + i] * f[j];
+        const T r = (a0 + a1) + (a2 + a3);
+        if (ng == 1) y[i] = r;
+        else scratch[t] = r;
+    }
+    if (ng > 1) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) {
+            T acc = scratch[i];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * n + i];
+            y[i] = acc;
+        }
+    }
+    __syncthreads();
+}
+
 // y = U^T f, U upper triangular (incl. diagonal):  y[i] = sum_{j<=i} U[j][i] f[j]
 template <typename T, int NT>
 __device__ __forceinline__ void ut_mv(const T *U, int ld, int n, const T *f, T *y) {
@@ -173,12 +278,11 @@ __device__ bool chol_inv(T *H, int ld, int n, T *xd) {
 // Reduced KKT solve with the stored inverse factors:
 //   [H A^T; A 0] [dz; dnu] = [f; r4]
 //   y = L^{-1} f;  dnu = S^{-1} (Wt y - r4);  dz = L^{-T} (y - Wt^T dnu)
-// y [n], t1/t2 [p] are scratch.  Results in dz [n], dnu [p].
+// y [n], t1/t2 [p] and scratch [NT] are scratch.  Results in dz [n], dnu [p].
 template <typename T, int NT>
 __device__ void kkt_solve(const T *U, int ldu, const T *Wt, const T *US, int n, int p,
-                          const T *f, const T *r4, T *y, T *t1, T *t2, T *dz, T *dnu) {
-    ut_mv<T, NT>(U, ldu, n, f, y);
-    __syncthreads();
+                          const T *f, const T *r4, T *y, T *t1, T *t2, T *dz, T *dnu, T *scratch) {
+    ut_mv_split<T, NT>(U, ldu, n, f, y, scratch);
     if (p > 0) {
         mv_rows<T, NT>(Wt, n, p, n, y, t1);
         __syncthreads();

@@ -39,13 +39,13 @@ constexpr int kGChunk = 32;          // rows of G staged per LDS chunk when G is
 // LDS regions of the policies (elements of T, after the driver's vectors).
 template <bool HL>
 struct GenericLayout {
-    int xd, xdp, y, t1, t2, tq, H, end;
+    int xd, xdp, y, t1, t2, tq, scr, H, end;
     __host__ __device__ GenericLayout(int base, int n, int m, int p) {
         (void)m;
         int o = base;
         const int N = pad4(n), Pp = pad4(p);
         xd = o; o += N; xdp = o; o += Pp; y = o; o += N; t1 = o; o += Pp; t2 = o; o += Pp;
-        tq = o; o += N;
+        tq = o; o += N; scr = o; o += 64 * kTiledWaves;
         o = (o + 15) & ~15;
         H = o;
         end = HL ? o + n * h_ld(n) : o;
@@ -82,7 +82,7 @@ struct GenericFactor {
     T *H;
     int ldh;
     T *U_state, *Dst, *Wt, *US;
-    T *xd, *xdp, *y, *t1, *t2, *tq;
+    T *xd, *xdp, *y, *t1, *t2, *tq, *scr;
 
     __device__ GenericFactor(const Prob<T> &P, T *sm, int base) {
         n = P.n; m = P.m; p = P.p;
@@ -94,7 +94,7 @@ struct GenericFactor {
         US = (T *)(P.state + SL.off_US);
         const GenericLayout<HL> L(base, n, m, p);
         xd = sm + L.xd; xdp = sm + L.xdp; y = sm + L.y; t1 = sm + L.t1; t2 = sm + L.t2;
-        tq = sm + L.tq;
+        tq = sm + L.tq; scr = sm + L.scr;
         if (HL) { H = sm + L.H; ldh = h_ld(n); } else { H = U_state; ldh = u_ld(n); }
     }
     __device__ __forceinline__ void prepare() {}
@@ -105,7 +105,7 @@ struct GenericFactor {
         return ok;
     }
     __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
-        kkt_solve<T, NT>(H, ldh, Wt, US, n, p, f, r4, y, t1, t2, dz, dnu);
+        kkt_solve<T, NT>(H, ldh, Wt, US, n, p, f, r4, y, t1, t2, dz, dnu, scr);
     }
     __device__ __forceinline__ void gt_mv(const T *v, T *out) {
         mv_cols<T, NT>(G, n, m, n, v, out);
@@ -171,76 +171,6 @@ struct Mfma<float> {
 };
 
 
-
-// out[i] = sum_{k<rows} M[k][i] v[k] for i < cols.  When cols < NT the rows
-// are split into up to eight groups whose partial sums (scratch, NT entries)
-// are added in a fixed order; otherwise one thread per column.
-template <typename T, int NT>
-__device__ __forceinline__ void colsum_split(const T *M, int ld, int rows, int cols, const T *v, T *out,
-                                             T *scratch) {
-    const int ng = cols > 0 ? max(1, min(NT / cols, 8)) : 1;
-    const int chunk = (rows + ng - 1) / ng;
-    for (int t = threadIdx.x; t < ng * cols; t += NT) {
-        const int q = t / cols, i = t - q * cols;
-        const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int k = k0;
-        for (; k + 3 < k1; k += 4) {
-            a0 += M[(size_t)k * ld + i] * v[k];
-            a1 += M[(size_t)(k + 1) * ld + i] * v[k + 1];
-            a2 += M[(size_t)(k + 2) * ld + i] * v[k + 2];
-            a3 += M[(size_t)(k + 3) * ld + i] * v[k + 3];
-        }
-        for (; k < k1; ++k) a0 += M[(size_t)k * ld + i] * v[k];
-        const T r = (a0 + a1) + (a2 + a3);
-        if (ng == 1) out[i] = r;
-        else scratch[t] = r;
-    }
-    if (ng > 1) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < cols; i += NT) {
-            T acc = scratch[i];
-            for (int q = 1; q < ng; ++q) acc += scratch[q * cols + i];
-            out[i] = acc;
-        }
-    }
-    __syncthreads();
-}
-
-// out[k] = sum_{i<cols} M[k][i] x[i] for k < rows (M in LDS, odd ld): the
-// columns are split into up to eight groups when rows < NT.
-template <typename T, int NT>
-__device__ __forceinline__ void rowdot_split(const T *M, int ld, int rows, int cols, const T *x, T *out,
-                                             T *scratch) {
-    const int ng = rows > 0 ? max(1, min(NT / rows, 8)) : 1;
-    const int chunk = (cols + ng - 1) / ng;
-    for (int t = threadIdx.x; t < ng * rows; t += NT) {
-        const int q = t / rows, k = t - q * rows;
-        const int i0 = q * chunk, i1 = min(cols, i0 + chunk);
-        const T *row = M + (size_t)k * ld;
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int i = i0;
-        for (; i + 3 < i1; i += 4) {
-            a0 += row[i] * x[i];
-            a1 += row[i + 1] * x[i + 1];
-            a2 += row[i + 2] * x[i + 2];
-            a3 += row[i + 3] * x[i + 3];
-        }
-        for (; i < i1; ++i) a0 += row[i] * x[i];
-        const T r = (a0 + a1) + (a2 + a3);
-        if (ng == 1) out[k] = r;
-        else scratch[t] = r;
-    }
-    if (ng > 1) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < rows; k += NT) {
-            T acc = scratch[k];
-            for (int q = 1; q < ng; ++q) acc += scratch[q * rows + k];
-            out[k] = acc;
-        }
-    }
-    __syncthreads();
-}
 
 // Which tiles a wavefront holds (see the grid comment above).
 template <int NTL>
