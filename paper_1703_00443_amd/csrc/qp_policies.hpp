@@ -172,6 +172,109 @@ struct Mfma<float> {
 
 
 
+// ---------------------------------------------------------------------------
+// Cholesky of a 16x16 SPD block fused with the inverse of its factor, in one
+// wavefront.  Register exchange only: DPP row_newbcast (lane k of every row of
+// 16 lanes) and the gfx950 permlane16/32 swaps (one row of 16 lanes to all four).
+//
+// Chain layout (both element types): lane 16 g + c holds column c, rows
+// g + 4 r (r = 0..3) of
+//   a: the symmetric trailing block, A[row][c] (entries with row or column
+//      below the current step may hold anything: they are never read again),
+//   x: X^T, X = L^{-1}, seeded with the unit diagonal and exact zeros below it.
+// Step k (A^(k) the trailing block, v = A^(k)[k][c], p = A^(k)[k][k]):
+//   a[r] -= A^(k)[row][k] v / p                     (Cholesky trailing update)
+//   x[r]  = c == k ? x[r] / sqrt(p)                 (column k of X^T final)
+//         : c >  k ? x[r] - X^T[row][k] v / p       (forward substitution)
+//         :          x[r]                           (finished columns)
+// Only registers that can hold a row > k (a) or a row <= k (x) are touched.
+template <typename T>
+__device__ __forceinline__ T chain_rsqrt(T x) {
+    if constexpr (sizeof(T) == 8) {
+        const double y = __builtin_amdgcn_rsq(x);  // hardware estimate + one Newton step
+        return y * (1.5 - 0.5 * x * y * y);
+    } else {
+        const float y = __builtin_amdgcn_rsqf(x);
+        return y * (1.5f - 0.5f * x * y * y);
+    }
+}
+template <int SRC>
+__device__ __forceinline__ unsigned row_bcast16(unsigned v) {  // lane SRC of each row of 16
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + SRC, 0xf, 0xf, false);
+}
+template <int SG>
+__device__ __forceinline__ unsigned group_bcast(unsigned v) {  // row SG of 16 lanes to all rows
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);  // rows {0,0,2,2} / {1,1,3,3}
+    const unsigned y = (SG & 1) ? a[1] : a[0];
+    const auto b = __builtin_amdgcn_permlane32_swap(y, y, false, false);  // rows {0,1,0,1} / {2,3,2,3}
+    return (SG & 2) ? b[1] : b[0];
+}
+template <int SRC, typename T>
+__device__ __forceinline__ T row_bcast16(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = row_bcast16<SRC>((unsigned)u), hi = row_bcast16<SRC>((unsigned)(u >> 32));
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, row_bcast16<SRC>(__builtin_bit_cast(unsigned, v)));
+    }
+}
+template <int SG, typename T>
+__device__ __forceinline__ T group_bcast(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = group_bcast<SG>((unsigned)u), hi = group_bcast<SG>((unsigned)(u >> 32));
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, group_bcast<SG>(__builtin_bit_cast(unsigned, v)));
+    }
+}
+template <typename T, int K>
+__device__ __forceinline__ void chain_steps(T *a, T *x, int c, bool &bad) {
+    if constexpr (K < 16) {
+        const T v = group_bcast<(K & 3)>(a[K >> 2]);  // A[K][c]
+        const T p = row_bcast16<K>(v);                 // A[K][K]
+        bad |= !(p > T(0)) || !isfinite(p);
+        const T inv = chain_rsqrt(p);
+        const T wc = v * (inv * inv);
+        const T wcm = (c > K) ? wc : T(0);
+        const T sc = (c == K) ? inv : T(1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (4 * r + 3 > K) a[r] = a[r] - row_bcast16<K>(a[r]) * wc;
+            if (4 * r <= K) x[r] = x[r] * sc - row_bcast16<K>(x[r]) * wcm;
+        }
+        chain_steps<T, K + 1>(a, x, c, bad);
+    }
+}
+// `pan`: the block inside an LDS panel (ld 17) whose lower triangle (incl.
+// diagonal) holds the SPD block.  On return x[r] holds X^T[g + 4 r][c] (valid
+// for g + 4 r <= c) and the upper triangle (incl. diagonal) of `pan` holds X^T
+// once the caller has waited for the stores.  Returns false (uniformly) on a
+// non-positive or non-finite pivot.
+template <typename T>
+__device__ __forceinline__ bool diag_chol_inv16(T *pan, int lane, T *x) {
+    const int g = lane >> 4, c = lane & 15;
+    T a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = g + 4 * r;
+        a[r] = pan[(row > c ? row : c) * 17 + (row > c ? c : row)];
+        x[r] = (row == c) ? T(1) : T(0);
+    }
+    // the loads complete before any lane's later stores to the panel
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    bool bad = false;
+    chain_steps<T, 0>(a, x, c, bad);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = g + 4 * r;
+        if (row <= c) pan[row * 17 + c] = x[r];
+    }
+    return !bad;
+}
+
 // Which tiles a wavefront holds (see the grid comment above).
 template <int NTL>
 struct TileMap {
@@ -340,52 +443,38 @@ struct TiledFactor {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) panel[(16 * R + Mfma<T>::row(g, r)) * 17 + c] = sq[s][r];
             }
-            // ---- (1b) the diagonal tile, 16 dependent steps in one wavefront
+            // ---- (1b) the diagonal tile: factor and inverse in the one wavefront that holds it
             if (w == wd) {
                 v4 t = {0, 0, 0, 0};
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
                     if (s == sd) t = sq[s];
-                int rl[4];
+                T *pan = panel + 16 * P * 17;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) rl[r] = Mfma<T>::row(g, r);
-                bool bad = false;
-                for (int kk = 0; kk < 16; ++kk) {
-                    if (c == kk) {
+                for (int r = 0; r < 4; ++r) pan[Mfma<T>::row(g, r) * 17 + c] = t[r];
+                // wave-local LDS exchange: the stores must land before other lanes load
+                __builtin_amdgcn_s_waitcnt(0);
+                __builtin_amdgcn_wave_barrier();
+                T xr[4];
+                const bool ok = diag_chol_inv16<T>(pan, lane, xr);
+                if constexpr (sizeof(T) == 8) {
+                    // the f64 accumulator layout is the chain layout (row g + 4 r)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) dbuf[rl[r]] = t[r];
-                    }
-                    // The column written by four lanes must have landed before
-                    // the other lanes read it: a wave-local LDS store is not
-                    // ordered before later loads without an explicit wait.
+                    for (int r = 0; r < 4; ++r)
+                        if (Mfma<T>::row(g, r) <= c) t[r] = xr[r];
+                } else {
                     __builtin_amdgcn_s_waitcnt(0);
                     __builtin_amdgcn_wave_barrier();
-                    const T vk = dbuf[kk];
-                    const T vc = dbuf[c];
-                    T vr[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) vr[r] = dbuf[rl[r]];
-                    bad |= !(vk > T(0)) || !isfinite(vk);
-                    const T inv = Mfma<T>::rsqrt(vk);
-                    const T wc = vc * (inv * inv);
-                    const bool upd_c = c > kk, fin_c = c == kk;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int row = rl[r];
-                        const T v = (row == kk) ? T(1) : vr[r];
-                        const bool upd = upd_c && (row >= c || row <= kk);
-                        const T xu = upd ? t[r] - v * wc : t[r];
-                        t[r] = fin_c ? v * inv : xu;
+                        const int row = Mfma<T>::row(g, r);
+                        if (row <= c) t[r] = pan[row * 17 + c];  // X_PP^T (upper incl. diagonal)
                     }
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __builtin_amdgcn_wave_barrier();
                 }
-                if (bad && c == 0 && g == 0) *flag = 1;
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
                     if (s == sd) sq[s] = t;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) panel[(16 * P + rl[r]) * 17 + c] = t[r];
+                if (!ok && lane == 0) *flag = 1;
             }
             __syncthreads();
             if (*flag) return false;

@@ -193,50 +193,16 @@ struct StreamFactor {
             }
             __syncthreads();
             lane_ids();
-            // ---- (1b) the diagonal tile, 16 dependent steps in one wavefront
+            // ---- (1b) the diagonal tile: factor and inverse in one wavefront
             if (w == (P & 7)) {
-                int rl[4];
-                v4 t;
+                T xr[4];
+                const bool ok = diag_chol_inv16<T>(panel + 16 * P * 17, lane, xr);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    rl[r] = Mfma<T>::row(g, r);
-                    t[r] = panel[(16 * P + rl[r]) * 17 + c];
+                    const int row = g + 4 * r;
+                    if (row <= c) U[(size_t)(16 * P + row) * ldu + 16 * P + c] = xr[r];
                 }
-                bool bad = false;
-                for (int kk = 0; kk < 16; ++kk) {
-                    if (c == kk) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) dbuf[rl[r]] = t[r];
-                    }
-                    // wave-local LDS exchange: wait for the stores before the loads
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __builtin_amdgcn_wave_barrier();
-                    const T vk = dbuf[kk];
-                    const T vc = dbuf[c];
-                    T vr[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) vr[r] = dbuf[rl[r]];
-                    bad |= !(vk > T(0)) || !isfinite(vk);
-                    const T inv = Mfma<T>::rsqrt(vk);
-                    const T wc = vc * (inv * inv);
-                    const bool upd_c = c > kk, fin_c = c == kk;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = rl[r];
-                        const T v = (row == kk) ? T(1) : vr[r];
-                        const bool upd = upd_c && (row >= c || row <= kk);
-                        const T xu = upd ? t[r] - v * wc : t[r];
-                        t[r] = fin_c ? v * inv : xu;
-                    }
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __builtin_amdgcn_wave_barrier();
-                }
-                if (bad && c == 0 && g == 0) *flag = 1;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    panel[(16 * P + rl[r]) * 17 + c] = t[r];
-                    U[(size_t)(16 * P + rl[r]) * ldu + 16 * P + c] = t[r];
-                }
+                if (!ok && lane == 0) *flag = 1;
             }
             __syncthreads();
             if (*flag) return false;
