@@ -26,23 +26,77 @@ namespace qpmi {
 
 __host__ __device__ constexpr int pad4(int x) { return (x + 3) & ~3; }
 
+// Wavefront reductions by register exchange only (no LDS): DPP quad_perm
+// (lane ^ 1, lane ^ 2), DPP row_half_mirror and row_mirror (within rows of 16),
+// then the gfx950 permlane16/32 swaps across the four rows.  Every step
+// combines a value with a partner whose own step combines the same two values,
+// so all 64 lanes end with bit-identical results; the order is fixed.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = dpp_u32<CTRL>((unsigned)u), hi = dpp_u32<CTRL>((unsigned)(u >> 32));
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, dpp_u32<CTRL>(__builtin_bit_cast(unsigned, v)));
+    }
+}
+// partner values across rows: {own row pair's even row, odd row} (permlane16)
+// and {lower half, upper half} (permlane32), as (first, second)
+template <bool HALF32, typename T>
+__device__ __forceinline__ void row_swap(T v, T &first, T &second) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        unsigned lo0, lo1, hi0, hi1;
+        if constexpr (HALF32) {
+            const auto l = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+            const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+            lo0 = l[0]; lo1 = l[1]; hi0 = h[0]; hi1 = h[1];
+        } else {
+            const auto l = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+            const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+            lo0 = l[0]; lo1 = l[1]; hi0 = h[0]; hi1 = h[1];
+        }
+        first = __builtin_bit_cast(T, ((unsigned long long)hi0 << 32) | lo0);
+        second = __builtin_bit_cast(T, ((unsigned long long)hi1 << 32) | lo1);
+    } else {
+        const unsigned u = __builtin_bit_cast(unsigned, v);
+        if constexpr (HALF32) {
+            const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+            first = __builtin_bit_cast(T, (unsigned)r[0]); second = __builtin_bit_cast(T, (unsigned)r[1]);
+        } else {
+            const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+            first = __builtin_bit_cast(T, (unsigned)r[0]); second = __builtin_bit_cast(T, (unsigned)r[1]);
+        }
+    }
+}
+template <typename T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+    v = op(v, dpp_move<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = op(v, dpp_move<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = op(v, dpp_move<0x141>(v));  // row_half_mirror
+    v = op(v, dpp_move<0x140>(v));  // row_mirror
+    T a, b;
+    row_swap<false>(v, a, b);       // rows (0,1) and (2,3): a = even row, b = odd row
+    v = op(a, b);
+    row_swap<true>(v, a, b);        // halves: a = rows 0-1, b = rows 2-3
+    return op(a, b);
+}
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return wave_reduce(v, [](T x, T y) { return x + y; });
 }
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, [](T x, T y) { return fmax(x, y); });
 }
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, [](T x, T y) { return fmin(x, y); });
 }
 
 // Workgroup reductions of up to three values at once (sum, max, min), the
@@ -87,17 +141,39 @@ __device__ __forceinline__ void mv_cols(const T *__restrict__ M, int ld, int row
     }
 }
 
-// y[r] = sum_{c<cols} M[r][c] x[c]   (one wavefront per row, lanes over columns)
+// Sum over a row of 16 lanes (DPP quad_perm, row_half_mirror, row_mirror);
+// every lane of the row ends with the same value.
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    return v;
+}
+
+// y[r] = sum_{c<cols} M[r][c] x[c]: 16 lanes per row (four rows per wavefront
+// at a time), four loads in flight per lane, in-row DPP reduction.  Measured
+// 3-4x faster than a wavefront per row for global M.  No barrier at the end.
 template <typename T, int NT>
 __device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int rows, int cols,
                                         const T *x, T *y) {
     constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int r = w; r < rows; r += NW) {
-        T acc = 0;
-        for (int c = lane; c < cols; c += 64) acc += M[(size_t)r * ld + c] * x[c];
-        acc = wave_sum(acc);
-        if (lane == 0) y[r] = acc;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+    for (int r0 = 4 * w; r0 < rows; r0 += 4 * NW) {
+        const int r = r0 + g < rows ? r0 + g : rows - 1;
+        const T *row = M + (size_t)r * ld;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int c = cl;
+        for (; c + 48 < cols; c += 64) {
+            a0 += row[c] * x[c];
+            a1 += row[c + 16] * x[c + 16];
+            a2 += row[c + 32] * x[c + 32];
+            a3 += row[c + 48] * x[c + 48];
+        }
+        for (; c < cols; c += 16) a0 += row[c] * x[c];
+        const T s = row16_sum((a0 + a1) + (a2 + a3));
+        if (cl == 0 && r0 + g < rows) y[r0 + g] = s;
     }
 }
 
@@ -112,16 +188,20 @@ __device__ __forceinline__ void colsum_split(const T *M, int ld, int rows, int c
     for (int t = threadIdx.x; t < ng * cols; t += NT) {
         const int q = t / cols, i = t - q * cols;
         const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0;
         int k = k0;
-        for (; k + 3 < k1; k += 4) {
+        for (; k + 7 < k1; k += 8) {
             a0 += M[(size_t)k * ld + i] * v[k];
             a1 += M[(size_t)(k + 1) * ld + i] * v[k + 1];
             a2 += M[(size_t)(k + 2) * ld + i] * v[k + 2];
             a3 += M[(size_t)(k + 3) * ld + i] * v[k + 3];
+            a4 += M[(size_t)(k + 4) * ld + i] * v[k + 4];
+            a5 += M[(size_t)(k + 5) * ld + i] * v[k + 5];
+            a6 += M[(size_t)(k + 6) * ld + i] * v[k + 6];
+            a7 += M[(size_t)(k + 7) * ld + i] * v[k + 7];
         }
         for (; k < k1; ++k) a0 += M[(size_t)k * ld + i] * v[k];
-        const T r = (a0 + a1) + (a2 + a3);
+        const T r = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
         if (ng == 1) out[i] = r;
         else scratch[t] = r;
     }
@@ -216,16 +296,25 @@ __device__ __forceinline__ void ut_mv(const T *U, int ld, int n, const T *f, T *
     }
 }
 
-// x = U y:  x[j] = sum_{i>=j} U[j][i] y[i]   (wavefront per row)
+// x = U y:  x[j] = sum_{i>=j} U[j][i] y[i]   (16 lanes per row, as mv_rows)
 template <typename T, int NT>
 __device__ __forceinline__ void u_mv(const T *U, int ld, int n, const T *y, T *x) {
     constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int j = w; j < n; j += NW) {
-        T acc = 0;
-        for (int i = j + lane; i < n; i += 64) acc += U[(size_t)j * ld + i] * y[i];
-        acc = wave_sum(acc);
-        if (lane == 0) x[j] = acc;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+    for (int j0 = 4 * w; j0 < n; j0 += 4 * NW) {
+        const int j = j0 + g < n ? j0 + g : n - 1;
+        const T *row = U + (size_t)j * ld;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int i = j + cl;
+        for (; i + 48 < n; i += 64) {
+            a0 += row[i] * y[i];
+            a1 += row[i + 16] * y[i + 16];
+            a2 += row[i + 32] * y[i + 32];
+            a3 += row[i + 48] * y[i + 48];
+        }
+        for (; i < n; i += 16) a0 += row[i] * y[i];
+        const T s = row16_sum((a0 + a1) + (a2 + a3));
+        if (cl == 0 && j0 + g < n) x[j0 + g] = s;
     }
 }
 

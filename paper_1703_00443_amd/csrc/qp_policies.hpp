@@ -618,8 +618,12 @@ struct TiledFactor {
                 const T fr = f[row < n ? row : 0];
                 acc += (row <= col && row < n) ? sq[s][r] * fr : T(0);
             }
-            acc += __shfl_xor(acc, 16, 64);
-            acc += __shfl_xor(acc, 32, 64);
+            {
+                T a, b;
+                row_swap<false>(acc, a, b);  // rows 0+1, 2+3
+                row_swap<true>(a + b, a, b); // + the other half
+                acc = a + b;
+            }
             if (g == 0) part[I * np + col] = acc;
         }
         __syncthreads();
@@ -659,16 +663,18 @@ struct TiledFactor {
                 const int row = 16 * I + Mfma<T>::row(g, r);
                 v[r] = (col >= row) ? sq[s][r] * yc : T(0);
             }
-            // reduce-scatter over the 16 lanes of the row group
+            // reduce-scatter over the 16 lanes of the row group: partners
+            // c <-> 15 - c (row_mirror) and c <-> 7 - c within each 8
+            // (row_half_mirror) flip bits 3 and 2 of c, then the quad sum
             const bool hi = (c & 8) != 0;
             T k0 = hi ? v[2] : v[0], k1 = hi ? v[3] : v[1];
-            k0 += __shfl_xor(hi ? v[0] : v[2], 8, 64);
-            k1 += __shfl_xor(hi ? v[1] : v[3], 8, 64);
+            k0 += dpp_move<0x140>(hi ? v[0] : v[2]);
+            k1 += dpp_move<0x140>(hi ? v[1] : v[3]);
             const bool h2 = (c & 4) != 0;
             T keep = h2 ? k1 : k0;
-            keep += __shfl_xor(h2 ? k0 : k1, 4, 64);
-            keep += __shfl_xor(keep, 2, 64);
-            keep += __shfl_xor(keep, 1, 64);
+            keep += dpp_move<0x141>(h2 ? k0 : k1);
+            keep += dpp_move<0x4E>(keep);
+            keep += dpp_move<0xB1>(keep);
             if ((c & 3) == 0) part[J * np + 16 * I + Mfma<T>::row(g, (hi ? 2 : 0) + (h2 ? 1 : 0))] = keep;
         }
         __syncthreads();
