@@ -330,7 +330,7 @@ __device__ __forceinline__ void u_mv(const T *U, int ld, int n, const T *y, T *x
 // triangle (incl. diagonal) holds U = L^{-T}.  Returns false (uniformly) on a
 // non-positive or non-finite pivot.
 template <typename T, int NT>
-__device__ bool chol_inv(T *H, int ld, int n, T *xd) {
+__device__ __forceinline__ bool chol_inv(T *H, int ld, int n, T *xd) {
     const int tid = threadIdx.x;
     for (int k = 0; k < n; ++k) {
         const T dkk = H[(size_t)k * ld + k];

@@ -108,15 +108,21 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     T *zp = sm + Lo.zp, *sp = sm + Lo.sp, *lp = sm + Lo.lp, *nup = sm + Lo.nup;
     T *red = sm + Lo.red;
     const T *__restrict__ A = P.A;
+    // the problem's pointers as plain locals (keeps the descriptor out of
+    // scratch memory in the larger policy instantiations)
+    const T *__restrict__ Pq = P.q, *__restrict__ Ph = P.h, *__restrict__ Pb = P.b;
+    const T *__restrict__ PQ = P.Q, *__restrict__ PG = P.G;
+    T *Pz = P.z, *Ps = P.s, *Plam = P.lam, *Pnu = P.nu;
+    const int Pout = P.out;
 
     // Input finiteness (one pass over every input).
     bool fin = true;
-    for (int e = tid; e < n * n; e += NT) fin &= isfinite(P.Q[e]);
-    for (int e = tid; e < m * n; e += NT) fin &= isfinite(P.G[e]);
+    for (int e = tid; e < n * n; e += NT) fin &= isfinite(PQ[e]);
+    for (int e = tid; e < m * n; e += NT) fin &= isfinite(PG[e]);
     for (int e = tid; e < p * n; e += NT) fin &= isfinite(A[e]);
-    for (int e = tid; e < n; e += NT) fin &= isfinite(P.q[e]);
-    for (int e = tid; e < m; e += NT) fin &= isfinite(P.h[e]);
-    for (int e = tid; e < p; e += NT) fin &= isfinite(P.b[e]);
+    for (int e = tid; e < n; e += NT) fin &= isfinite(Pq[e]);
+    for (int e = tid; e < m; e += NT) fin &= isfinite(Ph[e]);
+    for (int e = tid; e < p; e += NT) fin &= isfinite(Pb[e]);
     {
         T bad = fin ? T(0) : T(1), d0 = 0, d1 = 0;
         block_reduce3<T, NT>(bad, d0, d1, red);
@@ -148,16 +154,16 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             goto finish;
         }
         // f = -q + G^T h  (r1 = -q, r2 = 0, r3 = h, r4 = b)
-        fac.gt_mv(P.h, f);
-        for (int i = tid; i < n; i += NT) f[i] -= P.q[i];
-        for (int k = tid; k < p; k += NT) tp2[k] = P.b[k];
+        fac.gt_mv(Ph, f);
+        for (int i = tid; i < n; i += NT) f[i] -= Pq[i];
+        for (int k = tid; k < p; k += NT) tp2[k] = Pb[k];
         __syncthreads();
         fac.solve(f, tp2, z, nu);
         if (m > 0) {
             fac.g_mv(z, tm);
             T mns = pinf<T>(), mnl = pinf<T>(), dummy = 0;
             for (int k = tid; k < m; k += NT) {
-                const T sk = P.h[k] - tm[k];
+                const T sk = Ph[k] - tm[k];
                 s[k] = sk;
                 lam[k] = -sk;
                 mns = fmin(mns, sk);
@@ -191,14 +197,14 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         }
         T vsum = 0, vmax = 0, vmin = pinf<T>();
         for (int i = tid; i < n; i += NT) {
-            T acc = tn[i] + P.q[i] + rx[i];
+            T acc = tn[i] + Pq[i] + rx[i];
             if (p > 0) acc += tn2[i];
             rx[i] = -acc;
             vmax = fmax(vmax, fabs(acc));
             vmin = fmin(vmin, isfinite(acc) ? T(1) : T(0));
         }
         for (int k = tid; k < m; k += NT) {
-            const T r = -(tm[k] + s[k] - P.h[k]);
+            const T r = -(tm[k] + s[k] - Ph[k]);
             rz[k] = r;
             vmax = fmax(vmax, fabs(r));
             vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
@@ -206,7 +212,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             D[k] = lam[k] / s[k];
         }
         for (int k = tid; k < p; k += NT) {
-            const T r = -(ry[k] - P.b[k]);
+            const T r = -(ry[k] - Pb[k]);
             ry[k] = r;
             vmax = fmax(vmax, fabs(r));
             vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
@@ -298,10 +304,10 @@ store_factor:
     fac.finish(D);
 
 finish:
-    for (int i = tid; i < n; i += NT) P.z[i] = z[i];
-    for (int k = tid; k < m; k += NT) { P.s[k] = s[k]; P.lam[k] = lam[k]; }
-    for (int k = tid; k < p; k += NT) P.nu[k] = nu[k];
-    if (tid == 0) { status[P.out] = st; iters[P.out] = it; }
+    for (int i = tid; i < n; i += NT) Pz[i] = z[i];
+    for (int k = tid; k < m; k += NT) { Ps[k] = s[k]; Plam[k] = lam[k]; }
+    for (int k = tid; k < p; k += NT) Pnu[k] = nu[k];
+    if (tid == 0) { status[Pout] = st; iters[Pout] = it; }
     __syncthreads();
 }
 

@@ -84,7 +84,7 @@ struct GenericFactor {
     T *U_state, *Dst, *Wt, *US;
     T *xd, *xdp, *y, *t1, *t2, *tq, *scr;
 
-    __device__ GenericFactor(const Prob<T> &P, T *sm, int base) {
+    __device__ __forceinline__ GenericFactor(const Prob<T> &P, T *sm, int base) {
         n = P.n; m = P.m; p = P.p;
         Q = P.Q; G = P.G; A = P.A;
         const StateLayout SL = state_layout(sizeof(T), n, m, p);
@@ -309,7 +309,7 @@ struct TiledFactor {
         w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: tile skips are scalar branches
     }
 
-    __device__ TiledFactor(const Prob<T> &P, T *sm, int base) {
+    __device__ __forceinline__ TiledFactor(const Prob<T> &P, T *sm, int base) {
         n = P.n; m = P.m; p = P.p;
         nt = (n + 15) / 16; np = 16 * nt; pt = (p + 15) / 16;
         Q = P.Q; Gsrc = P.G; A = P.A;

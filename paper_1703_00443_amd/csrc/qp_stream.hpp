@@ -60,7 +60,8 @@ __host__ __device__ inline bool stream_plan(int esz, int base, int n, int m, int
 template <typename T, bool EQ>
 struct StreamFactor {
     static constexpr int NT = 64 * kTiledWaves;
-    static constexpr int GT = 8;  // form(): tiles per wavefront and pass
+    static constexpr int GT = 8;   // form(): tiles per wavefront and pass
+    static constexpr int SE = 16;  // form(): elements of G staged per thread and chunk
     using v4 = typename Mfma<T>::v4;
     int n, m, p, nt, np, pt, ldg, lds, ldu, kc;
     bool s_lds;
@@ -76,7 +77,7 @@ struct StreamFactor {
         w = __builtin_amdgcn_readfirstlane(t >> 6);
     }
 
-    __device__ StreamFactor(const Prob<T> &P, T *sm, int base) {
+    __device__ __forceinline__ StreamFactor(const Prob<T> &P, T *sm, int base) {
         n = P.n; m = P.m; p = P.p;
         nt = (n + 15) / 16; np = 16 * nt; pt = (p + 15) / 16;
         Q = P.Q; Gsrc = P.G; A = P.A;
@@ -118,6 +119,12 @@ struct StreamFactor {
             for (int r = 0; r < 4; ++r) U[(size_t)(16 * I + Mfma<T>::row(g, r)) * ldu + 16 * J + c] = T(0);
         }
         const int NL = nt * (nt + 1) / 2;
+        // chunk rows: what the LDS plan allows and at most SE elements per
+        // thread; staged element i of this thread sits at row-major position
+        // threadIdx.x + i NT of the chunk, walked without divisions
+        const int kcr = min(kc, max(4, ((SE * NT) / np) & ~3));
+        const int q_np = NT / np, r_np = NT - q_np * np;
+        const int k_base = threadIdx.x / np, c_base = threadIdx.x - k_base * np;
         for (int t0 = 0; t0 < NL; t0 += kTiledWaves * GT) {
             int ti[GT], tj[GT];
             v4 acc[GT];
@@ -126,6 +133,9 @@ struct StreamFactor {
                 const int t = t0 + w * GT + j;
                 int I = -1, J = 0;
                 if (t < NL) lower_tile(t, I, J);
+                // wave-uniform: keep the tile coordinates in scalar registers
+                I = __builtin_amdgcn_readfirstlane(I);
+                J = __builtin_amdgcn_readfirstlane(J);
                 ti[j] = I; tj[j] = J;
                 v4 a = {0, 0, 0, 0};
                 if (I >= 0) {
@@ -140,12 +150,30 @@ struct StreamFactor {
                 }
                 acc[j] = a;
             }
-            for (int k0 = 0; k0 < m; k0 += kc) {
-                const int rows = min(kc, m - k0), rp = (rows + 3) & ~3;
+            for (int k0 = 0; k0 < m; k0 += kcr) {
+                const int rows = min(kcr, m - k0), rp = (rows + 3) & ~3;
+                // all SE loads of this thread are issued before any store
+                T stg[SE];
+                {
+                    int k = k_base, col = c_base;
+#pragma unroll
+                    for (int i = 0; i < SE; ++i) {
+                        const bool v = k < rows && col < n;
+                        const T x = Gsrc[v ? (size_t)(k0 + k) * n + col : 0];
+                        stg[i] = v ? x : T(0);
+                        k += q_np; col += r_np;
+                        if (col >= np) { col -= np; ++k; }
+                    }
+                }
                 __syncthreads();  // previous chunk consumed
-                for (int e = threadIdx.x; e < rp * np; e += NT) {
-                    const int k = e / np, i = e - k * np;
-                    gbuf[k * ldg + i] = (k < rows && i < n) ? Gsrc[(size_t)(k0 + k) * n + i] : T(0);
+                {
+                    int k = k_base, col = c_base;
+#pragma unroll
+                    for (int i = 0; i < SE; ++i) {
+                        if (k < rp) gbuf[k * ldg + col] = stg[i];
+                        k += q_np; col += r_np;
+                        if (col >= np) { col -= np; ++k; }
+                    }
                 }
                 __syncthreads();
                 lane_ids();
