@@ -1,0 +1,87 @@
+"""Host-side logic with no GPU: the seeded generators, the autotune table
+lookup, the uneven-batch cost model, and the bench's algorithmic counts."""
+import json
+import os
+
+import numpy as np
+
+from paper_1703_00443_amd import synth
+from paper_1703_00443_amd.autotune import BUCKETS, AutotuneTable, bucket_of, candidates
+
+
+def test_problem_regenerates_alone():
+    """Problem i of a batch is drawn from its own stream [seed, i], so it is the
+    same alone and inside any batch (what the alone-vs-mix tests rely on)."""
+    b = synth.make_batch(seed=321, B=5, n=7, m=9, p=2)
+    one = synth.one_problem(np.random.default_rng([321, 3]), 7, 9, 2)
+    for k, v in zip(("Q", "q", "A", "b", "G", "h", "g"), one):
+        np.testing.assert_array_equal(getattr(b, k)[3], v)
+
+
+def test_generator_is_feasible_and_convex():
+    """h = G z0 + s0 with s0 > 0 and b = A z0: z0 is strictly feasible; Q is
+    symmetric positive definite (smallest eigenvalue at least 1e-3)."""
+    rng = np.random.default_rng([11, 0])
+    Q, q, A, b, G, h, g = synth.one_problem(rng, 12, 30, 3, row_normalize=True)
+    np.testing.assert_allclose(Q, Q.T)
+    assert np.linalg.eigvalsh(Q).min() >= 1e-3 - 1e-12
+    np.testing.assert_allclose(np.linalg.norm(G, axis=1), 1.0)
+    rng = np.random.default_rng([11, 0])
+    L = rng.standard_normal((12, 12)); rng.standard_normal(12); rng.standard_normal((30, 12))
+    rng.standard_normal((3, 12)); z0 = rng.standard_normal(12)
+    assert np.all(h - G @ z0 > 0)
+    np.testing.assert_allclose(A @ z0, b)
+
+
+def test_workload_shapes():
+    dims = synth.varlen_dims(4096, 300)
+    assert all(8 <= n <= 256 and m == 2 * n and 0 <= p <= n // 4 for n, m, p in dims)
+    sd = synth.serving_dims(4, 300)
+    assert all(16 <= n <= 512 and n <= m <= 2 * n and 0 <= p <= n // 8 for n, m, p, _ in sd)
+    frac_bwd = np.mean([d[3] for d in sd])
+    assert 0.35 < frac_bwd < 0.65
+
+
+def test_autotune_buckets_and_lookup(tmp_path):
+    assert bucket_of(1) == 0 and bucket_of(16) == 0 and bucket_of(17) == 1
+    assert bucket_of(BUCKETS[-1][1]) == len(BUCKETS) - 1
+    for i, (lo, hi) in enumerate(BUCKETS):
+        assert bucket_of(lo) == i and bucket_of(hi) == i
+    t = AutotuneTable({"f32": {"noeq": {"4": 3}, "eq": {"4": 4}}})
+    assert t.variant_for("f32", 100, 200, 0) == 3
+    assert t.variant_for("f32", 100, 200, 7) == 4
+    assert t.variant_for("f64", 100, 200, 0) == 0       # no entry: automatic plan
+    path = os.path.join(str(tmp_path), "t.json")
+    t.save(path)
+    assert AutotuneTable.load(path).data == json.load(open(path))
+    # candidate variants: register tiles only within their size limits
+    assert 3 in candidates(128, "f64") and 3 not in candidates(129, "f64")
+    assert 3 in candidates(256, "f32") and 3 not in candidates(257, "f32")
+    assert 4 in candidates(1000, "f64")
+
+
+def test_committed_table_is_valid():
+    t = AutotuneTable.load()
+    for dk, per in t.data.items():
+        assert dk in ("f32", "f64")
+        for eq, buckets in per.items():
+            assert eq in ("eq", "noeq")
+            for b, v in buckets.items():
+                assert 0 <= int(b) < len(BUCKETS) and v in (1, 2, 3, 4)
+
+
+def test_algorithmic_flops_counts():
+    """Counts of the bench's roofline at the paper-scale shape, by hand: one
+    iterate costs n(n+1)m + n^3/3 (factor) + residual + 2 solves."""
+    import bench
+    n = m = 100
+    fac = n * (n + 1) * m + n ** 3 / 3
+    res = 2 * n * n + 4 * n * m
+    sol = 4 * n * m + 2 * n * n
+    assert abs(bench.algorithmic_flops(n, m, 0, [0]) - (2 * fac + res + sol)) < 1e-6
+    assert abs(bench.algorithmic_flops(n, m, 0, [3]) - (5 * fac + 4 * res + 7 * sol)) < 1e-6
+    per_iter = fac + res + 2 * sol
+    assert abs(per_iter - 1.52e6) / 1.52e6 < 0.01   # 1.52 Mflop per iterate at this shape
+    # backward bytes: read Q, G, z, lam, s, dl/dz and the factor (U, D); write
+    # dQ, dq, dG, dh  ->  3 n^2 + 2 m n + 3 n + 4 m elements = 50700 at this shape
+    assert bench.backward_bytes(n, m, 0, 8) == 8 * 50700
