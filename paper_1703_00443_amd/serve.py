@@ -141,6 +141,7 @@ class Server:
         self.bytes_in_flight = 0
         self.stats = {"admitted": 0, "rejected": 0, "launches": 0, "max_bytes_in_flight": 0,
                       "max_concurrent_launches": 0, "max_queue": 0}
+        self.failed: Optional[BaseException] = None
         self._stop = threading.Event()
         self._lock = threading.Lock()
         self._thread = threading.Thread(target=self._loop, name="qp-server", daemon=True)
@@ -155,6 +156,9 @@ class Server:
         fp = footprint_bytes(n, m, p, self.esz, need_backward)
         req = Request(problem, need_backward, None if dl_dz is None else np.asarray(dl_dz), fp,
                       time.perf_counter(), dims=(n, m, p))
+        if self.failed is not None:
+            req.future.set_exception(RuntimeError("server stopped after an error: %r" % (self.failed,)))
+            return req.future
         if need_backward and req.dl_dz is None:
             req.future.set_exception(ValueError("need_backward requires dl_dz"))
             return req.future
@@ -236,11 +240,30 @@ class Server:
         st["max_concurrent_launches"] = max(st["max_concurrent_launches"], len(self.inflight))
         return True
 
+    def _fail_all(self, exc: BaseException):
+        """An unexpected scheduler error: every request not yet completed gets
+        the exception, and the server stops accepting work."""
+        self.failed = exc
+        for _, _, reqs, _ in self.inflight:
+            for r in reqs:
+                if not r.future.done():
+                    r.future.set_exception(exc)
+        self.inflight = []
+        self._drain_incoming()
+        for r in self.waiting:
+            if not r.future.done():
+                r.future.set_exception(exc)
+        self.waiting = collections.deque()
+
     def _loop(self):
         while True:
-            self._drain_incoming()
-            self._complete()
-            launched = self._admit_and_launch()
+            try:
+                self._drain_incoming()
+                self._complete()
+                launched = self._admit_and_launch()
+            except Exception as e:  # keep no future waiting on a dead scheduler
+                self._fail_all(e)
+                break
             if self._stop.is_set() and not self.inflight and not self.waiting and self.incoming.empty():
                 break
             if not launched:

@@ -130,3 +130,23 @@ def test_backward_needs_upstream_gradient():
 def test_percentiles():
     p = percentiles(list(range(1, 101)))
     assert p["p50"] == 50 and p["p99"] == 99
+
+
+class _BrokenReady(FakeBackend):
+    """A backend whose completion query fails after the first launch."""
+
+    def ready(self, h):
+        raise RuntimeError("event query failed")
+
+
+def test_scheduler_error_fails_every_pending_request():
+    srv = Server(backend=_BrokenReady(delay=0.0), hbm_budget=1 << 30, max_inflight=1)
+    probs = synth.make_varlen(5, [(4, 6, 0), (5, 7, 1), (6, 8, 0)])
+    futs = [srv.submit(P) for P in probs]
+    for f in futs:
+        with pytest.raises(RuntimeError):
+            f.result(timeout=30)
+    assert srv.failed is not None
+    with pytest.raises(RuntimeError):
+        srv.submit(probs[0]).result(timeout=5)
+    srv.close()
