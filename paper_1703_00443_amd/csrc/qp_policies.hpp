@@ -57,14 +57,13 @@ struct GenericLayout {
 // (ld p | 1) with its pivot scratch and two p-vectors.
 template <bool GL>
 struct TiledLayout {
-    int part, yv, xv, panel, scratch, dbuf, flag, S, xdp, pv1, pv2, G, end;
+    int part, yv, xv, panel, scratch, flag, S, xdp, pv1, pv2, G, end;
     __host__ __device__ TiledLayout(int base, int n, int m, int p) {
         const int nt = (n + 15) / 16, np = 16 * nt;
         int o = base;
         part = o; o += nt * np; yv = o; o += np; xv = o; o += np;
         panel = o; o += np * 17;
         scratch = o; o += 64 * kTiledWaves;
-        dbuf = o; o += 16;
         flag = o; o += 4;
         S = o; o += p > 0 ? p * h_ld(p) : 0;
         xdp = o; o += pad4(p); pv1 = o; o += pad4(p); pv2 = o; o += pad4(p);
@@ -144,14 +143,6 @@ template <>
 struct Mfma<double> {
     typedef double v4 __attribute__((ext_vector_type(4)));
     __host__ __device__ static constexpr int row(int g, int r) { return g + 4 * r; }
-    // 1/sqrt(x), x > 0: hardware estimate refined by two Newton steps (to ~1 ulp)
-    __device__ static __forceinline__ double rsqrt(double x) {
-        double y = __builtin_amdgcn_rsq(x);
-        const double hx = 0.5 * x;
-        y = y * (1.5 - hx * y * y);
-        y = y * (1.5 - hx * y * y);
-        return y;
-    }
     __device__ static __forceinline__ v4 mma(double a, double b, v4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -160,11 +151,6 @@ template <>
 struct Mfma<float> {
     typedef float v4 __attribute__((ext_vector_type(4)));
     __host__ __device__ static constexpr int row(int g, int r) { return 4 * g + r; }
-    __device__ static __forceinline__ float rsqrt(float x) {
-        float y = __builtin_amdgcn_rsqf(x);
-        y = y * (1.5f - 0.5f * x * y * y);
-        return y;
-    }
     __device__ static __forceinline__ v4 mma(float a, float b, v4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -296,7 +282,7 @@ struct TiledFactor {
     const T *Q, *Gsrc, *A;
     const T *G;  // LDS copy (GL) or the staging chunk
     T *Ust, *Dst, *Wt, *US;  // state: U (row-major, ld n), D, Wt (p x n), US (p x p)
-    T *part, *yv, *xv, *panel, *scratch, *dbuf, *S, *xdp, *pv1, *pv2;
+    T *part, *yv, *xv, *panel, *scratch, *S, *xdp, *pv1, *pv2;
     int *flag;
     int w, lane, g, c;
     v4 sq[NS];
@@ -320,7 +306,7 @@ struct TiledFactor {
         US = (T *)(P.state + SL.off_US);
         const TiledLayout<GL> L(base, n, m, p);
         part = sm + L.part; yv = sm + L.yv; xv = sm + L.xv;
-        panel = sm + L.panel; scratch = sm + L.scratch; dbuf = sm + L.dbuf;
+        panel = sm + L.panel; scratch = sm + L.scratch;
         S = sm + L.S; xdp = sm + L.xdp; pv1 = sm + L.pv1; pv2 = sm + L.pv2;
         flag = reinterpret_cast<int *>(sm + L.flag);
         G = sm + L.G; ldg = np + 1; lds = h_ld(p); ldu = u_ld(n);

@@ -21,7 +21,7 @@ namespace qpmi {
 // s_lds: the Schur block S sits in LDS (sharing the staging buffer); otherwise
 // it is factored in place in the US region of the state.
 struct StreamLayout {
-    int yv, xv, panel, scratch, dbuf, flag, xdp, pv1, pv2, buf, end;
+    int yv, xv, panel, scratch, flag, xdp, pv1, pv2, buf, end;
     __host__ __device__ StreamLayout(int base, int n, int m, int p, int kc, bool s_lds) {
         (void)m;
         const int nt = (n + 15) / 16, np = 16 * nt;
@@ -29,7 +29,6 @@ struct StreamLayout {
         yv = o; o += np; xv = o; o += np;
         panel = o; o += np * 17;
         scratch = o; o += 64 * kTiledWaves;
-        dbuf = o; o += 16;
         flag = o; o += 4;
         xdp = o; o += pad4(p); pv1 = o; o += pad4(p); pv2 = o; o += pad4(p);
         o = (o + 15) & ~15;
@@ -61,13 +60,14 @@ template <typename T, bool EQ>
 struct StreamFactor {
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr int GT = 8;   // form(): tiles per wavefront and pass
-    static constexpr int SE = 16;  // form(): elements of G staged per thread and chunk
+    static constexpr int SE = sizeof(T) == 4 ? 32 : 16;  // form(): G elements staged per thread and chunk
     using v4 = typename Mfma<T>::v4;
     int n, m, p, nt, np, pt, ldg, lds, ldu, kc;
     bool s_lds;
     const T *Q, *Gsrc, *A;
     T *U, *Dst, *Wt, *US;
-    T *yv, *xv, *panel, *scratch, *dbuf, *xdp, *pv1, *pv2, *gbuf, *S;
+    T *yv, *xv, *panel, *scratch, *xdp, *pv1, *pv2, *gbuf, *S;
+    int fcap;  // form(): elements from the panel to the end of the layout (idle during the formation)
     int *flag;
     int w, lane, g, c;
 
@@ -90,9 +90,10 @@ struct StreamFactor {
         (void)stream_plan(sizeof(T), base, n, m, p, P.lds_limit, &kc, &s_lds);
         const StreamLayout L(base, n, m, p, kc, s_lds);
         yv = sm + L.yv; xv = sm + L.xv; panel = sm + L.panel; scratch = sm + L.scratch;
-        dbuf = sm + L.dbuf; flag = reinterpret_cast<int *>(sm + L.flag);
+        flag = reinterpret_cast<int *>(sm + L.flag);
         xdp = sm + L.xdp; pv1 = sm + L.pv1; pv2 = sm + L.pv2;
-        gbuf = sm + L.buf;
+        gbuf = sm + L.panel;
+        fcap = L.end - L.panel;
         ldg = np + 1; ldu = u_ld(n);
         if (s_lds) { S = sm + L.buf; lds = h_ld(p); } else { S = US; lds = p; }
         lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
@@ -119,10 +120,13 @@ struct StreamFactor {
             for (int r = 0; r < 4; ++r) U[(size_t)(16 * I + Mfma<T>::row(g, r)) * ldu + 16 * J + c] = T(0);
         }
         const int NL = nt * (nt + 1) / 2;
-        // chunk rows: what the LDS plan allows and at most SE elements per
+        // chunk rows: what fits in the region from the panel to the end of the
+        // layout (the panel, the solve vectors and the Schur block are idle
+        // during the formation), at most 64 and at most SE elements per
         // thread; staged element i of this thread sits at row-major position
         // threadIdx.x + i NT of the chunk, walked without divisions
-        const int kcr = min(kc, max(4, ((SE * NT) / np) & ~3));
+        const int kcf = min(64, (fcap / ldg) & ~3);
+        const int kcr = min(kcf, max(4, ((SE * NT) / np) & ~3));
         const int q_np = NT / np, r_np = NT - q_np * np;
         const int k_base = threadIdx.x / np, c_base = threadIdx.x - k_base * np;
         for (int t0 = 0; t0 < NL; t0 += kTiledWaves * GT) {
@@ -182,10 +186,18 @@ struct StreamFactor {
                     const T *Gk = gbuf + k * ldg;
                     const int kg = k0 + k;
                     const T dk = D[kg < m ? kg : m - 1] * T(kg < m ? 1 : 0);
+                    // all operand loads first (unused tiles read row 0), then the MFMAs
+                    T av[GT], bv[GT];
+#pragma unroll
+                    for (int j = 0; j < GT; ++j) {
+                        const int I = ti[j] < 0 ? 0 : ti[j];
+                        av[j] = Gk[16 * I + c];
+                        bv[j] = dk * Gk[16 * tj[j] + c];
+                    }
 #pragma unroll
                     for (int j = 0; j < GT; ++j) {
                         if (ti[j] < 0) continue;
-                        acc[j] = Mfma<T>::mma(Gk[16 * ti[j] + c], dk * Gk[16 * tj[j] + c], acc[j]);
+                        acc[j] = Mfma<T>::mma(av[j], bv[j], acc[j]);
                     }
                 }
             }

@@ -1,6 +1,6 @@
-"""Serving on the GPU: a Poisson stream of mixed-size requests (half with a
-backward) through the continuous-batching server; each result must equal the
-same request solved alone (same kernel variant => bitwise), and a sample is
+"""Serving on the GPU: a Poisson stream of 100 mixed-size requests (half with a
+backward) through the continuous-batching server; every result must equal the
+same request solved alone (same kernel variant => bitwise), and every tenth is
 checked against the oracle."""
 import time
 
@@ -18,7 +18,7 @@ def test_served_results_equal_alone_results():
     import torch
     from paper_1703_00443_amd.serve import Server
     from paper_1703_00443_amd.varlen import VarlenBatch
-    dims = synth.serving_dims(55, 48, n_lo=16, n_hi=128)
+    dims = synth.serving_dims(55, 100, n_lo=16, n_hi=192)
     probs = synth.make_varlen(55, [d[:3] for d in dims], dtype=np.float32)
     srv = Server(dtype=torch.float32, hbm_budget=1 << 30, max_inflight=3)
     rng = np.random.default_rng(1)
@@ -30,7 +30,7 @@ def test_served_results_equal_alone_results():
     srv.close()
     assert srv.stats["admitted"] == len(probs)
     assert srv.stats["launches"] > 1
-    for i in range(0, len(probs), 5):
+    for i in range(len(probs)):
         P = probs[i]
         one = VarlenBatch([P], dtype=torch.float32, table=srv.backend.table)
         one.forward()
@@ -43,6 +43,7 @@ def test_served_results_equal_alone_results():
         if dims[i][3]:
             np.testing.assert_array_equal(res[i]["dG"], a["dG"])
             np.testing.assert_array_equal(res[i]["dQ"], a["dQ"])
-        ref = oracle_replay(P, res[i]["iters"], np.float32)
-        assert z_err(res[i]["z"], ref["z"]) <= TOL_Z[np.float32]
         assert res[i]["latency"] > 0
+        if i % 10 == 0:
+            ref = oracle_replay(P, res[i]["iters"], np.float32)
+            assert z_err(res[i]["z"], ref["z"]) <= TOL_Z[np.float32]

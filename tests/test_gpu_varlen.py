@@ -10,8 +10,12 @@ from parity import TOL_G, TOL_Z, g_err, grad_scale, oracle_grads, oracle_replay,
 
 pytestmark = pytest.mark.gpu
 
+# every policy appears: register tiles (8x8 grid, and 16x16 in FP32 with and
+# without equality rows), streamed tiles (FP64 above 128, FP32 above 256), and
+# the degenerate shapes (no inequality rows, one variable)
 MIXED = [(1, 2, 0), (5, 9, 2), (16, 32, 0), (17, 34, 3), (40, 80, 0), (64, 128, 16), (100, 100, 0),
-         (128, 256, 0), (129, 200, 5), (33, 0, 4), (12, 24, 0), (90, 180, 22)]
+         (128, 256, 0), (129, 200, 5), (33, 0, 4), (12, 24, 0), (90, 180, 22), (200, 220, 30),
+         (300, 310, 10)]
 
 
 def _batch(dims, dtype, seed=90210, variants=None):
@@ -48,7 +52,7 @@ def test_alone_equals_in_mix_bitwise():
     vb.forward().backward(dl)
     torch.cuda.synchronize()
     from paper_1703_00443_amd.varlen import VarlenBatch
-    for i in (0, 3, 6, 8, 11):
+    for i in (0, 3, 6, 8, 11, 12, 13):
         one = VarlenBatch([probs[i]], dtype=torch.float32)
         one.forward().backward(one.pack_vectors([probs[i]["g"]]))
         torch.cuda.synchronize()
