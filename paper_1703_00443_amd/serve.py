@@ -1,6 +1,6 @@
 """Serving loop with continuous batching for QP layer requests.
 
-    srv = Server(dtype=torch.float32, hbm_budget=4 << 30, max_inflight=4)
+    srv = Server(dtype=torch.float32, hbm_budget=4 << 30, max_inflight=8)
     fut = srv.submit({"Q":..., "q":..., "G":..., "h":..., "A":..., "b":...},
                      need_backward=True, dl_dz=g)
     res = fut.result()        # dict: z, lam, nu, s, status, iters, grads (if asked), latency
@@ -15,11 +15,18 @@ other streams, so their work overlaps on the device.  A request larger than the
 whole budget is rejected at submission.  Each launch records an event; the
 scheduler completes the futures of a launch when its event has fired.
 
+A launch completes when its slowest problem does, so requests are split into
+size classes by nz (`class_bounds`) and a launch holds one class only; each
+class may occupy at most its share of the slots.  Small requests then never
+wait behind a large one's solve, and a burst of large requests cannot take
+every slot.
+
 The device work sits behind a small backend interface (`launch`, `ready`,
 `collect`) so that the scheduler can be exercised without a GPU.
 """
 from __future__ import annotations
 
+import bisect
 import collections
 import math
 import queue
@@ -45,6 +52,7 @@ class Request:
     t_arrival: float
     future: Future = field(default_factory=Future)
     dims: tuple = ()
+    cls: int = 0
 
 
 def footprint_bytes(n: int, m: int, p: int, esz: int, need_backward: bool) -> int:
@@ -57,6 +65,38 @@ def footprint_bytes(n: int, m: int, p: int, esz: int, need_backward: bool) -> in
     if need_backward:
         total += inputs + n + (n + m + p + 64)
     return int(total * esz + 4096)
+
+
+_DEDICATED: Dict[int, list] = {}
+_DEDICATED_LOCK = threading.Lock()
+
+
+def dedicated_stream(device_index: int, k: int):
+    """The k-th stream of a process-wide pool (per device) whose streams each get a
+    hardware queue of their own.  Streams that share a hardware queue run in
+    order, so a short launch would wait behind a long one on another slot; HIP
+    gives a stream created with a CU mask its own queue, and the full mask used
+    here leaves every compute unit to it.  Default priority.  The streams live
+    until the process ends (the caching allocator keeps blocks recorded on
+    them), so they are reused across servers."""
+    import ctypes
+    import os
+    import torch
+    with _DEDICATED_LOCK:
+        pool = _DEDICATED.setdefault(device_index, [])
+        while len(pool) <= k:
+            with torch.cuda.device(device_index):
+                torch.cuda.init()
+                hip = ctypes.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | ctypes.RTLD_GLOBAL)
+                cus = torch.cuda.get_device_properties(device_index).multi_processor_count
+                words = (cus + 31) // 32
+                mask = (ctypes.c_uint32 * words)(*([0xFFFFFFFF] * words))
+                s = ctypes.c_void_p()
+                rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(s), ctypes.c_uint32(words), mask)
+                if rc != 0:
+                    raise RuntimeError("hipExtStreamCreateWithCUMask failed: %d" % rc)
+                pool.append(torch.cuda.ExternalStream(s.value, device=torch.device("cuda", device_index)))
+        return pool[k]
 
 
 class DeviceBackend:
@@ -73,7 +113,9 @@ class DeviceBackend:
         self.esz = 8 if dtype == torch.float64 else 4
 
     def new_slot(self):
-        return self.torch.cuda.Stream(device=self.device)
+        idx = self.device.index if self.device.index is not None else 0
+        self._slots = getattr(self, "_slots", 0) + 1
+        return dedicated_stream(idx, self._slots - 1)
 
     def launch(self, slot, reqs: List[Request]):
         torch = self.torch
@@ -123,8 +165,8 @@ class DeviceBackend:
 
 
 class Server:
-    def __init__(self, backend=None, dtype=None, hbm_budget: int = 4 << 30, max_inflight: int = 4,
-                 max_batch: int = 512, idle_sleep: float = 2e-4):
+    def __init__(self, backend=None, dtype=None, hbm_budget: int = 4 << 30, max_inflight: int = 8,
+                 max_batch: int = 512, idle_sleep: float = 2e-4, class_bounds=(64, 128, 256)):
         if backend is None:
             import torch
             backend = DeviceBackend(dtype if dtype is not None else torch.float32)
@@ -133,14 +175,20 @@ class Server:
         self.budget = int(hbm_budget)
         self.max_batch = max_batch
         self.idle_sleep = idle_sleep
+        # class c holds requests with class_bounds[c-1] < nz <= class_bounds[c]
+        self.class_bounds = tuple(sorted(int(b) for b in class_bounds))
+        n_cls = len(self.class_bounds) + 1
+        self.class_cap = max(1, max_inflight // n_cls)
+        self.class_inflight = [0] * n_cls
         self.slots = [backend.new_slot() for _ in range(max_inflight)]
         self.free_slots = collections.deque(range(max_inflight))
         self.waiting: "collections.deque[Request]" = collections.deque()
         self.incoming: "queue.Queue[Request]" = queue.Queue()
-        self.inflight: List = []  # (slot index, handle, requests, bytes)
+        self.inflight: List = []  # (slot index, handle, requests, bytes, class)
         self.bytes_in_flight = 0
         self.stats = {"admitted": 0, "rejected": 0, "launches": 0, "max_bytes_in_flight": 0,
-                      "max_concurrent_launches": 0, "max_queue": 0}
+                      "max_concurrent_launches": 0, "max_queue": 0, "launch_host_s": 0.0,
+                      "launches_per_class": [0] * n_cls}
         self.failed: Optional[BaseException] = None
         self._stop = threading.Event()
         self._lock = threading.Lock()
@@ -155,7 +203,8 @@ class Server:
         p = 0 if problem.get("A") is None else int(np.asarray(problem["A"]).reshape(-1, n).shape[0])
         fp = footprint_bytes(n, m, p, self.esz, need_backward)
         req = Request(problem, need_backward, None if dl_dz is None else np.asarray(dl_dz), fp,
-                      time.perf_counter(), dims=(n, m, p))
+                      time.perf_counter(), dims=(n, m, p),
+                      cls=bisect.bisect_left(self.class_bounds, n))
         if self.failed is not None:
             req.future.set_exception(RuntimeError("server stopped after an error: %r" % (self.failed,)))
             return req.future
@@ -186,7 +235,7 @@ class Server:
 
     def _complete(self):
         still = []
-        for slot, handle, reqs, nbytes in self.inflight:
+        for slot, handle, reqs, nbytes, cls in self.inflight:
             if self.backend.ready(handle):
                 try:
                     results = self.backend.collect(handle, reqs)
@@ -201,50 +250,66 @@ class Server:
                             r.future.set_exception(e)
                 self.bytes_in_flight -= nbytes
                 self.free_slots.append(slot)
+                self.class_inflight[cls] -= 1
             else:
-                still.append((slot, handle, reqs, nbytes))
+                still.append((slot, handle, reqs, nbytes, cls))
         self.inflight = still
 
+    def _next_class(self) -> Optional[int]:
+        """Class of the oldest waiting request whose class has a slot share left."""
+        for r in self.waiting:
+            if not r.future.cancelled() and self.class_inflight[r.cls] < self.class_cap:
+                return r.cls
+        return None
+
     def _admit_and_launch(self) -> bool:
-        if not self.waiting or not self.free_slots:
-            return False
-        batch, nbytes = [], 0
-        kept = collections.deque()
-        while self.waiting and len(batch) < self.max_batch:
-            r = self.waiting.popleft()
-            if r.future.cancelled():
+        launched = False
+        while self.waiting and self.free_slots:
+            cls = self._next_class()
+            if cls is None:
+                break
+            batch, nbytes = [], 0
+            kept = collections.deque()
+            for r in self.waiting:
+                if r.future.cancelled():
+                    continue
+                if (r.cls == cls and len(batch) < self.max_batch
+                        and self.bytes_in_flight + nbytes + r.footprint <= self.budget):
+                    batch.append(r)
+                    nbytes += r.footprint
+                else:
+                    kept.append(r)  # another class, or waits until memory frees up
+            self.waiting = kept
+            if not batch:
+                break
+            slot = self.free_slots.popleft()
+            t0 = time.perf_counter()
+            try:
+                handle = self.backend.launch(self.slots[slot], batch)
+            except Exception as e:
+                for r in batch:
+                    r.future.set_exception(e)
+                self.free_slots.append(slot)
+                launched = True
                 continue
-            if self.bytes_in_flight + nbytes + r.footprint <= self.budget:
-                batch.append(r)
-                nbytes += r.footprint
-            else:
-                kept.append(r)  # waits until memory frees up
-        kept.extend(self.waiting)
-        self.waiting = kept
-        if not batch:
-            return False
-        slot = self.free_slots.popleft()
-        try:
-            handle = self.backend.launch(self.slots[slot], batch)
-        except Exception as e:
-            for r in batch:
-                r.future.set_exception(e)
-            self.free_slots.append(slot)
-            return True
-        self.inflight.append((slot, handle, batch, nbytes))
-        self.bytes_in_flight += nbytes
-        st = self.stats
-        st["admitted"] += len(batch)
-        st["launches"] += 1
-        st["max_bytes_in_flight"] = max(st["max_bytes_in_flight"], self.bytes_in_flight)
-        st["max_concurrent_launches"] = max(st["max_concurrent_launches"], len(self.inflight))
-        return True
+            st = self.stats
+            st["launch_host_s"] += time.perf_counter() - t0
+            self.inflight.append((slot, handle, batch, nbytes, cls))
+            self.bytes_in_flight += nbytes
+            self.class_inflight[cls] += 1
+            st["admitted"] += len(batch)
+            st["launches"] += 1
+            st["launches_per_class"][cls] += 1
+            st["max_bytes_in_flight"] = max(st["max_bytes_in_flight"], self.bytes_in_flight)
+            st["max_concurrent_launches"] = max(st["max_concurrent_launches"], len(self.inflight))
+            launched = True
+        return launched
 
     def _fail_all(self, exc: BaseException):
         """An unexpected scheduler error: every request not yet completed gets
         the exception, and the server stops accepting work."""
         self.failed = exc
-        for _, _, reqs, _ in self.inflight:
+        for _, _, reqs, _, _ in self.inflight:
             for r in reqs:
                 if not r.future.done():
                     r.future.set_exception(exc)

@@ -32,6 +32,16 @@ def cost_estimate(n: int, m: int, p: int) -> float:
     return n * (n + 1) * m + n ** 3 / 3.0 + n * n * p + p ** 3 / 3.0
 
 
+def _to_device(t: torch.Tensor, dev: torch.device) -> torch.Tensor:
+    """Host tensor to `dev` without blocking the host: a pageable copy would wait
+    for all earlier work on the stream (e.g. the forward of the same batch)."""
+    if t.device == dev:
+        return t
+    if dev.type == "cuda" and t.device.type == "cpu":
+        return t.pin_memory().to(dev, non_blocking=True)
+    return t.to(dev)
+
+
 class VarlenBatch:
     def __init__(self, problems: Sequence[Dict], dtype: torch.dtype = torch.float32,
                  device: Optional[torch.device] = None, variants: Optional[Sequence[int]] = None,
@@ -39,20 +49,19 @@ class VarlenBatch:
         dev = device or torch.device("cuda:0")
         self.dtype, self.device = dtype, dev
         self.count = len(problems)
-        esz = 8 if dtype == torch.float64 else 4
         descs = (qb.qp_problem_desc * max(1, self.count))()
         self.dims = []
         off_in = 0
         off_z = off_l = off_n = 0
         off_state = 0
-        chunks = []
+        arrays = []  # (offset, array or None, size) in packing order
         for i, P in enumerate(problems):
             Q = np.asarray(P["Q"])
             n = Q.shape[0]
             G = P.get("G")
             A = P.get("A")
-            m = 0 if G is None else int(np.asarray(G).reshape(-1, n).shape[0])
-            p = 0 if A is None else int(np.asarray(A).reshape(-1, n).shape[0])
+            m = 0 if G is None else int(np.asarray(G).size // n)
+            p = 0 if A is None else int(np.asarray(A).size // n)
             d = descs[i]
             d.nz, d.nineq, d.neq = n, m, p
             if variants is not None:
@@ -61,27 +70,39 @@ class VarlenBatch:
                 d.variant = int(table.variant_for(dtype, n, m, p))
             else:
                 d.variant = 0
-            for key, shape in (("Q", (n, n)), ("q", (n,)), ("A", (p, n)), ("b", (p,)),
-                               ("G", (m, n)), ("h", (m,))):
+            for key, size in (("Q", n * n), ("q", n), ("A", p * n), ("b", p), ("G", m * n), ("h", m)):
                 setattr(d, key, off_in)
-                v = P.get(key)
-                arr = np.zeros(shape) if v is None else np.asarray(v, dtype=np.float64).reshape(shape)
-                chunks.append(arr.reshape(-1))
-                off_in += int(np.prod(shape))
+                arrays.append((off_in, P.get(key), size))
+                off_in += size
             d.z, d.lam, d.nu = off_z, off_l, off_n
             off_z += n; off_l += m; off_n += p
             d.state = off_state
             off_state += qb.state_bytes(dtype, n, m, p)
             self.dims.append((n, m, p))
-        npdt = np.float64 if dtype == torch.float64 else np.float32
-        host = np.concatenate(chunks).astype(npdt) if chunks else np.zeros(1, npdt)
-        self.base_in = torch.from_numpy(host).to(dev)
+        # one cast-and-copy per array into a (pinned, when the target is a GPU) staging
+        # buffer of the target dtype, then one asynchronous copy to the device
+        pinned = dev.type == "cuda"
+        host_t = torch.empty(max(1, off_in), dtype=dtype, pin_memory=pinned)
+        host = host_t.numpy()
+        for off, v, size in arrays:
+            if not size:
+                continue
+            if v is None:
+                host[off:off + size] = 0
+                continue
+            a = np.asarray(v).reshape(-1)
+            if a.size != size:
+                raise ValueError("array of %d elements where the problem's dims need %d"
+                                 % (a.size, size))
+            np.copyto(host[off:off + size], a, casting="unsafe")
+        self._host_in = host_t  # kept alive until the copy below has run
+        self.base_in = host_t.to(dev, non_blocking=pinned)
         self.descs_host = descs
         raw = bytes(memoryview(descs))[: ctypes.sizeof(qb.qp_problem_desc) * self.count]
-        self.descs_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev) if raw else \
-            torch.zeros(1, dtype=torch.uint8, device=dev)
+        self.descs_dev = _to_device(torch.frombuffer(bytearray(raw), dtype=torch.uint8), dev) if raw \
+            else torch.zeros(1, dtype=torch.uint8, device=dev)
         order = sorted(range(self.count), key=lambda i: -cost_estimate(*self.dims[i]))
-        self.order = torch.tensor(order, dtype=torch.int32, device=dev)
+        self.order = _to_device(torch.tensor(order, dtype=torch.int32), dev)
         self.z = torch.zeros(max(1, off_z), dtype=dtype, device=dev)
         self.lam = torch.zeros(max(1, off_l), dtype=dtype, device=dev)
         self.s = torch.zeros(max(1, off_l), dtype=dtype, device=dev)
@@ -89,7 +110,7 @@ class VarlenBatch:
         self.state = torch.zeros(max(1, off_state), dtype=torch.uint8, device=dev)
         self.status = torch.zeros(max(1, self.count), dtype=torch.int32, device=dev)
         self.iters = torch.zeros(max(1, self.count), dtype=torch.int32, device=dev)
-        self.grad = torch.zeros_like(self.base_in)
+        self.grad = torch.zeros(self.base_in.shape, dtype=dtype, device=dev)
         fws, bws, _ = self.workspace_bytes()
         self.fws = torch.zeros(max(1, fws), dtype=torch.uint8, device=dev)
         self.bws = torch.zeros(max(1, bws), dtype=torch.uint8, device=dev)
@@ -121,9 +142,10 @@ class VarlenBatch:
         the inputs."""
         o = opts if opts is not None else qb.default_opts(self.dtype)
         P = qb._ptr
-        g = dl_dz.to(device=self.device, dtype=self.dtype).contiguous()
+        g = _to_device(dl_dz.to(dtype=self.dtype).contiguous(), self.device)
         self._dl = g
-        self._need = None if need is None else need.to(device=self.device, dtype=torch.int32).contiguous()
+        self._need = None if need is None else \
+            _to_device(need.to(dtype=torch.int32).contiguous(), self.device)
         rc = qb.load_library().qp_backward_varlen(
             qb.dtype_code(self.dtype), self.count, P(self.descs_dev), ctypes.addressof(self.descs_host),
             P(self._need), P(self.base_in), ctypes.byref(o), P(self.z), P(self.lam), P(self.nu), P(self.s),
@@ -150,8 +172,19 @@ class VarlenBatch:
 
     def pack_vectors(self, vecs: List[np.ndarray]) -> torch.Tensor:
         """Concatenate per-problem z-shaped vectors (e.g. dl/dz) in packing order."""
-        npdt = np.float64 if self.dtype == torch.float64 else np.float32
-        return torch.from_numpy(np.concatenate([np.asarray(v, dtype=npdt) for v in vecs])).to(self.device)
+        pinned = self.device.type == "cuda"
+        total = sum(n for n, _, _ in self.dims)
+        host_t = torch.empty(max(1, total), dtype=self.dtype, pin_memory=pinned)
+        host = host_t.numpy()
+        off = 0
+        for (n, _, _), v in zip(self.dims, vecs):
+            a = np.asarray(v).reshape(-1)
+            if a.size != n:
+                raise ValueError("vector of %d elements for a problem with nz = %d" % (a.size, n))
+            np.copyto(host[off:off + n], a, casting="unsafe")
+            off += n
+        self._host_vec = host_t  # kept alive until the copy below has run
+        return host_t[:total].to(self.device, non_blocking=pinned)
 
 
 def capture_graph(vb: VarlenBatch, dl_dz: torch.Tensor, need: Optional[torch.Tensor] = None,

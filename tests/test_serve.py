@@ -92,7 +92,7 @@ def test_budget_bounds_bytes_in_flight_and_queues_the_rest():
     fps = [footprint_bytes(d[0], d[1], d[2], 8, False) for d in dims]
     budget = 3 * max(fps)  # room for about three requests at a time
     be = FakeBackend(0.03)
-    srv = Server(backend=be, hbm_budget=budget, max_inflight=4)
+    srv = Server(backend=be, hbm_budget=budget, max_inflight=4, class_bounds=())
     futs = [srv.submit(P) for P in probs]
     for f in futs:
         f.result(timeout=60)
@@ -108,7 +108,7 @@ def test_arrivals_during_flight_overlap_launches():
     free slot before the earlier one completes (continuous batching)."""
     probs, _ = _problems(8)
     be = FakeBackend(0.2)
-    srv = Server(backend=be, hbm_budget=1 << 30, max_inflight=4)
+    srv = Server(backend=be, hbm_budget=1 << 30, max_inflight=4, class_bounds=())
     f0 = srv.submit(probs[0])
     time.sleep(0.05)
     f1 = srv.submit(probs[1])
@@ -150,3 +150,41 @@ def test_scheduler_error_fails_every_pending_request():
     with pytest.raises(RuntimeError):
         srv.submit(probs[0]).result(timeout=5)
     srv.close()
+
+
+def test_size_classes_launch_separately_and_share_slots():
+    """With class bounds, a launch holds requests of one size class only, and a
+    class never holds more than its share of the slots."""
+    probs, dims = _problems(24)
+    be = FakeBackend(0.02)
+    srv = Server(backend=be, hbm_budget=1 << 30, max_inflight=4, class_bounds=(5,), max_batch=3)
+    futs = [srv.submit(P) for P in probs]
+    for f in futs:
+        f.result(timeout=60)
+    srv.close()
+    for launch in be.launched:
+        classes = {0 if d[0] <= 5 else 1 for d in launch}
+        assert len(classes) == 1, launch
+    assert srv.stats["admitted"] == 24
+    assert all(c > 0 for c in srv.stats["launches_per_class"])
+    assert be.max_active <= 4 and srv.stats["max_concurrent_launches"] <= 4
+
+
+def test_large_burst_leaves_slots_for_small_requests():
+    """A burst of large requests takes at most its class's share of the slots, so a
+    small request that arrives during the burst launches at once."""
+    big = synth.make_varlen(8, [(7, 9, 0)] * 8)
+    small = synth.make_varlen(9, [(3, 4, 0)])
+    be = FakeBackend(0.3)
+    srv = Server(backend=be, hbm_budget=1 << 30, max_inflight=4, class_bounds=(5,), max_batch=1)
+    fb = [srv.submit(P) for P in big]
+    time.sleep(0.05)
+    t0 = time.perf_counter()
+    fs = srv.submit(small[0])
+    fs.result(timeout=30)
+    t_small = time.perf_counter() - t0
+    for f in fb:
+        f.result(timeout=60)
+    srv.close()
+    assert t_small < 0.3 + 0.2   # one device duration, not a wait behind the burst
+    assert srv.stats["launches_per_class"] == [1, 8]
