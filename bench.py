@@ -211,22 +211,103 @@ def bench_serving(args):
     return out
 
 
+def time_uniform(B, n, m, p, dtype, steps, warmup=2, seed=1100, serial=False):
+    """Forward / backward milliseconds per call of one uniform batch of the
+    paper's generator (row-normalised G), HIP events on the launch stream; with
+    `serial`, also the same B problems as B batch-1 calls with a host sync each."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd import synth
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    bnp = synth.make_batch(seed=seed, B=B, n=n, m=m, p=p, row_normalize=True)
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(npdt))).to(dev)
+    prob = qb.make_problem(T(bnp.Q), T(bnp.q), None, None, T(bnp.G), T(bnp.h))
+    g = T(bnp.g)
+    opts = qb.default_opts(tdt)
+    fw = qb.forward(prob, opts)
+    ws = torch.empty(max(1, qb.workspace_bytes(tdt, B, n, m, p, opts)[1]), dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        qb.forward(prob, opts, out=fw)
+        qb.backward(prob, fw, g, opts, ws=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record(stream)
+        qb.forward(prob, opts, out=fw)
+        ev[k][1].record(stream)
+        qb.backward(prob, fw, g, opts, ws=ws)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    out = {"fwd_ms": round(float(np.mean([a.elapsed_time(b) for a, b, _ in ev])), 4),
+           "bwd_ms": round(float(np.mean([b.elapsed_time(c) for _, b, c in ev])), 4),
+           "iters_mean": round(float(fw.iters.float().mean().item()), 3)}
+    if serial:
+        singles = [qb.make_problem(prob.Q[i:i + 1], prob.q[i:i + 1], None, None, prob.G[i:i + 1],
+                                   prob.h[i:i + 1]) for i in range(B)]
+        f1 = qb.forward(singles[0], opts)
+        ws1 = torch.empty(max(1, qb.workspace_bytes(tdt, 1, n, m, p, opts)[1]), dtype=torch.uint8,
+                          device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(B):
+            qb.forward(singles[i], opts, out=f1)
+            qb.backward(singles[i], f1, g[i:i + 1], opts, ws=ws1)
+            torch.cuda.synchronize()
+        out["serial_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    return out
+
+
+def bench_sweep(args):
+    """The two solver-timing experiments of Section 5.1 as extra rows: (1) a
+    batch of 128 QPs with nz = nineq in {10, 50, 100, 500}, forward and backward
+    time; (2) nz = nineq = 100 at batch sizes 1 .. 2048, batched calls against
+    the same problems solved one per call (host sync per call, up to 128)."""
+    steps = args.steps if args.steps != 20 else 10   # the paper averages 10 trials
+    dts = (args.dtype,) if args.dtype_given else ("f64", "f32")
+    rows_size, rows_batch = [], []
+    for dt in dts:
+        for n in (10, 50, 100, 500):
+            r = time_uniform(128, n, n, 0, dt, steps, seed=1100 + n)
+            rows_size.append({"dtype": dt, "batch": 128, "nz": n, "nineq": n, **r})
+            print("sweep size %s nz=%d: %s" % (dt, n, r), file=sys.stderr, flush=True)
+        for B in (1, 8, 32, 128, 512, 2048):
+            r = time_uniform(B, 100, 100, 0, dt, steps, seed=1200, serial=B <= 128)
+            r["batched_solves_per_s"] = round(B / ((r["fwd_ms"] + r["bwd_ms"]) * 1e-3), 1)
+            if "serial_ms" in r:
+                r["serial_solves_per_s"] = round(B / (r["serial_ms"] * 1e-3), 1)
+            rows_batch.append({"dtype": dt, "batch": B, "nz": 100, "nineq": 100, **r})
+            print("sweep batch %s B=%d: %s" % (dt, B, r), file=sys.stderr, flush=True)
+    return {"metric": "QP layer time vs size and vs batch (paper's solver-timing experiments)",
+            "unit": "ms per call", "n_gpus": 1, "steps": steps, "higher_is_better": False,
+            "data": "synthetic (seeded generator of the paper's timing experiment, row-normalised G)",
+            "config": {"workload": "sizes nz=nineq in {10,50,100,500} at batch 128; batch sizes "
+                                   "1..2048 at nz=nineq=100; neq=0; fwd and bwd timed apart"},
+            "size_sweep": rows_size, "batch_sweep": rows_batch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--dtype", choices=("f64", "f32"), default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--workload", choices=("paper", "uneven", "serving"), default="paper",
+    ap.add_argument("--workload", choices=("paper", "uneven", "serving", "sweep"), default="paper",
                     help="paper: the headline metric (default); uneven: 4096 QPs of mixed sizes in "
-                         "one persistent launch; serving: Poisson request stream, p50/p99 latency")
+                         "one persistent launch; serving: Poisson request stream, p50/p99 latency; "
+                         "sweep: the paper's size and batch-size timing experiments")
     ap.add_argument("--count", type=int, default=0, help="problems/requests for uneven/serving")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, run 3 device copies of this many MiB "
                          "(reference kernel for HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
+    args.dtype_given = args.dtype is not None
+    if args.dtype is None:
+        args.dtype = "f64"
     if args.gpus != 1:
         print("bench.py measures one GPU only: every QP is independent and this build runs on a "
               "single MI355X (see DESIGN.md for how the batch would shard); got --gpus %d"
@@ -245,6 +326,9 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps(bench_serving(args)), flush=True)
+        return
+    if args.workload == "sweep":
+        print(json.dumps(bench_sweep(args)), flush=True)
         return
     dev = torch.device("cuda:0")
     tdt = torch.float64 if args.dtype == "f64" else torch.float32

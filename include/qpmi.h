@@ -206,6 +206,15 @@ int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc 
 /* The hipError_t of the last QP_EHIP return on this thread (0 if none). */
 int32_t qp_last_hip_error(void);
 
+/* The factorization policy the forward runs for one problem of `dims` when
+ * `variant` (a QP_VARIANT_*, 0 = automatic) is requested, on the current
+ * device: *policy receives QP_VARIANT_GENERIC (factor in global memory),
+ * QP_VARIANT_LDS, QP_VARIANT_TILED or QP_VARIANT_STREAM, and *lds_bytes (may
+ * be NULL) the dynamic LDS of its workgroup.  The plan depends on the problem's
+ * own dims, the variant and the device's LDS size only.  Host-side; launches
+ * nothing.  Returns QP_OK, QP_EDTYPE, QP_EARG or QP_ETOOBIG (no policy fits). */
+int32_t qp_plan(qp_dtype dtype, qp_dims dims, int32_t variant, int32_t *policy, int32_t *lds_bytes);
+
 /* Library version as 10000*major + 100*minor + patch. */
 int32_t qp_version(void);
 

@@ -52,7 +52,7 @@ class qp_problem_desc(ctypes.Structure):
 
 EXPORTED = ("qp_default_opts", "qp_state_bytes", "qp_workspace_query", "qp_forward_batched",
             "qp_backward_batched", "qp_varlen_workspace_query", "qp_forward_varlen",
-            "qp_backward_varlen", "qp_last_hip_error", "qp_version")
+            "qp_backward_varlen", "qp_plan", "qp_last_hip_error", "qp_version")
 
 _lib = None
 
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
                                       vp, vp, sz, vp]
     lib.qp_backward_varlen.argtypes = [i32, i32, vp, vp, vp, vp, P(qp_opts), vp, vp, vp, vp, vp, vp,
                                        vp, vp, sz, vp]
+    lib.qp_plan.argtypes = [i32, qp_dims, i32, P(i32), P(i32)]
     lib.qp_last_hip_error.argtypes = []
     lib.qp_version.argtypes = []
     for name in EXPORTED:
@@ -119,6 +120,15 @@ def state_bytes(dt: torch.dtype, n: int, m: int, p: int) -> int:
     _check(load_library().qp_state_bytes(dtype_code(dt), qp_dims(n, m, p), ctypes.byref(v)),
            "qp_state_bytes")
     return int(v.value)
+
+
+def plan(dt: torch.dtype, n: int, m: int, p: int, variant: int = 0):
+    """(policy, lds_bytes): the factorization policy (a VARIANT_* code) the
+    forward runs for one problem of these dims on the current device."""
+    pol, lds = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load_library().qp_plan(dtype_code(dt), qp_dims(n, m, p), variant, ctypes.byref(pol),
+                                  ctypes.byref(lds)), "qp_plan")
+    return int(pol.value), int(lds.value)
 
 
 def workspace_bytes(dt: torch.dtype, batch: int, n: int, m: int, p: int, opts=None):

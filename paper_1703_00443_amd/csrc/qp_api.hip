@@ -39,6 +39,22 @@ int32_t qp_version(void) { return 100; }
 
 int32_t qp_last_hip_error(void) { return g_last_hip_error; }
 
+int32_t qp_plan(qp_dtype dtype, qp_dims d, int32_t variant, int32_t *policy, int32_t *lds_bytes) {
+    if (!dtype_ok(dtype)) return QP_EDTYPE;
+    if (!dims_ok(d) || !policy || variant < 0 || variant > QP_VARIANT_STREAM) return QP_EARG;
+    int lds = 0;
+    const int pol = fwd_plan(esize(dtype), d.nz, d.nineq, d.neq, variant, device_lds_limit(), &lds);
+    if (pol == kPolicyNone) return QP_ETOOBIG;
+    switch (pol) {
+        case kPolicyGenericGlobal: *policy = QP_VARIANT_GENERIC; break;
+        case kPolicyGenericLds: *policy = QP_VARIANT_LDS; break;
+        case kPolicyStream: *policy = QP_VARIANT_STREAM; break;
+        default: *policy = QP_VARIANT_TILED; break;
+    }
+    if (lds_bytes) *lds_bytes = lds;
+    return QP_OK;
+}
+
 int32_t qp_default_opts(qp_dtype dtype, qp_opts *o) {
     if (!o) return QP_EARG;
     if (!dtype_ok(dtype)) return QP_EDTYPE;

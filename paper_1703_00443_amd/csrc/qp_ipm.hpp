@@ -72,12 +72,15 @@ __device__ __forceinline__ Prob<T> fwd_problem(const FwdLaunch &L, int idx) {
 
 // LDS vector layout of the interior point driver, in elements of T.  The
 // policy's own LDS region starts at `end`.
+// The iteration's vectors in LDS.  The combined step of the slacks and duals
+// reuses w and tm (each entry is read there just before it is overwritten), and
+// the last iterate with a good factor is kept in the problem's own output
+// buffers, idle until the end; both keep LDS for the factorization policies.
 struct IpmLayout {
-    int z, rx, f, y, dza, dzc, tn, tn2;          // n-vectors
-    int s, lam, rz, D, dsa, dla, dsc, dlc, w, tm; // m-vectors
-    int nu, ry, dna, dnc, tp, tp2;               // p-vectors
-    int zp, sp, lp, nup;                         // last iterate with a good factor
-    int red;                                     // 64 reduction slots
+    int z, rx, f, y, dza, dzc, tn, tn2;  // n-vectors
+    int s, lam, rz, D, dsa, dla, w, tm;  // m-vectors
+    int nu, ry, dna, dnc, tp, tp2;       // p-vectors
+    int red;                             // 64 reduction slots
     int end;
     __host__ __device__ IpmLayout(int n, int m, int p) {
         const int N = pad4(n), M = pad4(m), Pp = pad4(p);
@@ -85,10 +88,9 @@ struct IpmLayout {
         z = o; o += N; rx = o; o += N; f = o; o += N; y = o; o += N; dza = o; o += N;
         dzc = o; o += N; tn = o; o += N; tn2 = o; o += N;
         s = o; o += M; lam = o; o += M; rz = o; o += M; D = o; o += M; dsa = o; o += M;
-        dla = o; o += M; dsc = o; o += M; dlc = o; o += M; w = o; o += M; tm = o; o += M;
+        dla = o; o += M; w = o; o += M; tm = o; o += M;
         nu = o; o += Pp; ry = o; o += Pp; dna = o; o += Pp; dnc = o; o += Pp; tp = o; o += Pp;
         tp2 = o; o += Pp;
-        zp = o; o += N; sp = o; o += M; lp = o; o += M; nup = o; o += Pp;
         red = o; o += 64;
         end = (o + 15) & ~15;
     }
@@ -102,10 +104,10 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     T *z = sm + Lo.z, *rx = sm + Lo.rx, *f = sm + Lo.f, *dza = sm + Lo.dza, *dzc = sm + Lo.dzc,
       *tn = sm + Lo.tn, *tn2 = sm + Lo.tn2;
     T *s = sm + Lo.s, *lam = sm + Lo.lam, *rz = sm + Lo.rz, *D = sm + Lo.D, *dsa = sm + Lo.dsa,
-      *dla = sm + Lo.dla, *dsc = sm + Lo.dsc, *dlc = sm + Lo.dlc, *w = sm + Lo.w, *tm = sm + Lo.tm;
+      *dla = sm + Lo.dla, *w = sm + Lo.w, *tm = sm + Lo.tm;
+    T *dsc = tm, *dlc = w;  // combined step, written over the entries just read
     T *nu = sm + Lo.nu, *ry = sm + Lo.ry, *dna = sm + Lo.dna, *dnc = sm + Lo.dnc,
       *tp = sm + Lo.tp, *tp2 = sm + Lo.tp2;
-    T *zp = sm + Lo.zp, *sp = sm + Lo.sp, *lp = sm + Lo.lp, *nup = sm + Lo.nup;
     T *red = sm + Lo.red;
     const T *__restrict__ A = P.A;
     // the problem's pointers as plain locals (keeps the descriptor out of
@@ -114,6 +116,9 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     const T *__restrict__ PQ = P.Q, *__restrict__ PG = P.G;
     T *Pz = P.z, *Ps = P.s, *Plam = P.lam, *Pnu = P.nu;
     const int Pout = P.out;
+    // last iterate with a good factor: the output buffers, each entry written
+    // and read back by the same thread
+    T *zp = Pz, *sp = Ps, *lp = Plam, *nup = Pnu;
 
     // Input finiteness (one pass over every input).
     bool fin = true;

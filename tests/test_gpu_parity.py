@@ -199,16 +199,35 @@ def test_big_tiles_fp32(dims, B):
 @pytest.mark.parametrize("dims,dtypes", [
     ((1, 3, 0), "both"), ((16, 16, 0), "both"), ((17, 40, 3), "both"), ((100, 100, 0), "both"),
     ((130, 260, 10), "both"), ((200, 200, 50), "both"), ((300, 300, 20), "f32"),
-    ((512, 600, 64), "f32"), ((200, 200, 150), "both"), ((256, 256, 200), "f32")])
+    ((512, 600, 64), "f32"), ((200, 200, 150), "both"), ((256, 256, 200), "f32"),
+    ((500, 500, 0), "both")])
 def test_stream_policy(dims, dtypes):
     """The streamed-tile policy (factor in the state buffer, 16x16 MFMA tiles
     streamed through registers, G staged through LDS): tile edges, equality
-    rows, sizes beyond the register-resident policies, and Schur blocks too
-    large for LDS (factored in the state: FP64 at neq=150, FP32 at neq=200)."""
+    rows, sizes beyond the register-resident policies, Schur blocks too large
+    for LDS (factored in the state: FP64 at neq=150, FP32 at neq=200), and the
+    largest size of the paper's layer-timing experiment (nz = nineq = 500) in
+    both precisions.  The library's plan query confirms the policy that ran."""
+    import torch
     from paper_1703_00443_amd import binding as qb
     n, m, p = dims
     B = 1 if n >= 300 else 2
     b = synth.make_batch(seed=8080 + n, B=B, n=n, m=m, p=p, row_normalize=True)
     for dtype in ((np.float64, np.float32) if dtypes == "both" else (np.float32,)):
+        tdt = torch.float64 if dtype == np.float64 else torch.float32
+        assert qb.plan(tdt, n, m, p, qb.VARIANT_STREAM)[0] == qb.VARIANT_STREAM, (dims, dtype)
         out = _run(b, dtype, opts_over={"variant": qb.VARIANT_STREAM})
         _check(b, out, dtype, range(B), need_grad=dtype == np.float64 or m >= n)
+
+
+def test_automatic_plan_by_size():
+    """The automatic plan: register tiles up to nz = 128 (FP32: 256), streamed
+    tiles beyond, in both precisions up to nz = nineq = 500."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    for tdt in (torch.float64, torch.float32):
+        assert qb.plan(tdt, 100, 100, 0)[0] == qb.VARIANT_TILED
+        assert qb.plan(tdt, 500, 500, 0)[0] == qb.VARIANT_STREAM
+        assert qb.plan(tdt, 300, 300, 20)[0] == qb.VARIANT_STREAM
+    assert qb.plan(torch.float32, 250, 400, 10)[0] == qb.VARIANT_TILED
+    assert qb.plan(torch.float64, 250, 400, 10)[0] == qb.VARIANT_STREAM
