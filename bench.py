@@ -135,13 +135,32 @@ def bench_uneven(args):
     st = vb.status[:count].cpu().numpy()
     it = vb.iters[:count].cpu().numpy()
     flops = sum(algorithmic_flops(n, m, p, [k]) for (n, m, p), k in zip(dims, it))
+    # per size bucket: the bucket's problems alone, one launch each (forward + backward)
+    buckets = []
+    edges = (8, 32, 64, 128, 192, 256)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        idx = [i for i, d in enumerate(dims) if (lo < d[0] <= hi) or (lo == 8 and d[0] == 8)]
+        if not idx:
+            continue
+        vbb = VarlenBatch([probs[i] for i in idx], dtype=torch.float32, table=AutotuneTable.load())
+        dlb = vbb.pack_vectors([probs[i]["g"] for i in idx])
+        gb = capture_graph(vbb, dlb)
+        gb.replay()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(args.steps):
+            gb.replay()
+        torch.cuda.synchronize()
+        elb = (time.perf_counter() - tb) / args.steps
+        buckets.append({"nz": "%d..%d" % (lo if lo == 8 else lo + 1, hi), "problems": len(idx),
+                        "ms": round(elb * 1e3, 3), "solves_per_s": round(len(idx) / elb, 1)})
     return {"metric": "uneven batch QP solves/s fwd+bwd", "value": round(count / el, 2),
             "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(el * 1e3, 3), "higher_is_better": True, "dtype": "f32",
             "data": "synthetic", "config": {"workload": "%d QPs, nz~U{8..256}, nineq=2nz, "
                                             "neq~U{0..nz/4}, one persistent launch, graph-captured"
                                             % count},
-            "fwd_algorithmic_tflops": round(flops / el / 1e12, 3),
+            "fwd_algorithmic_tflops": round(flops / el / 1e12, 3), "per_bucket": buckets,
             "status_counts": np.bincount(st, minlength=5).tolist(), "iters_mean": float(it.mean())}
 
 
