@@ -75,8 +75,10 @@ typedef struct {
 /* Solver options (qp_default_opts fills them per dtype). */
 typedef struct {
     int32_t max_iter;     /* Newton steps after the initial point (default 20)          */
-    int32_t refine_steps; /* iterative-refinement steps in the backward solve
-                             (default 1 for F64, 3 for F32)                              */
+    int32_t refine_steps; /* backward solve: F64, steps of iterative refinement on the
+                             unreduced K_sym residual (default 1); F32, the FP64 projected
+                             CG preconditioned by the FP32 factor runs at most
+                             10 * refine_steps iterations (default 3, so 30)              */
     double tol;           /* stop when max(mu, |r_x|inf, |r_s|inf, |r_y|inf) <= tol,
                              mu = s^T lambda / nineq (default 1e-8 F64, 1e-3 F32)        */
     int32_t variant;      /* kernel variant: 0 = pick automatically, else a QP_VARIANT_* */
@@ -139,9 +141,12 @@ int32_t qp_forward_batched(qp_dtype dtype, int32_t batch, qp_dims dims, const qp
 /* ---- backward ----------------------------------------------------------------- */
 
 /* Gradients of a loss l through the QP solution (Section 3.1.1): solve
- * eq. grads-system with the stored factor (no new factorization) plus
- * opts->refine_steps steps of iterative refinement on the unreduced
- * symmetrised KKT residual, then form eq. grads:
+ * eq. grads-system with the stored factor (no new factorization).  F64: the
+ * factor's solve plus opts->refine_steps steps of iterative refinement on the
+ * unreduced symmetrised KKT residual.  F32: projected preconditioned conjugate
+ * gradients on the reduced system with FP64 vectors and products, the FP32
+ * factor as preconditioner (accurate where cond(H) eps32 exceeds 1).  Then
+ * eq. grads:
  *   dQ = 1/2 (d_z z^T + z d_z^T), dq = d_z, dA = d_nu z^T + nu d_z^T,
  *   db = -d_nu, dG = D(lam) d_lam z^T + lam d_z^T, dh = -D(lam) d_lam.
  * Inputs (device): data (the same problem data as the forward), z, lam, nu, s,

@@ -90,7 +90,146 @@ struct BwdLayout {
     }
 };
 
-size_t bwd_vec_lds_bytes(int esz, int n, int m, int p) { return (size_t)BwdLayout(n, m, p).end * esz; }
+// FP32 problems: the reduced adjoint system
+//     [H A^T; A 0] [d_z; d_nu] = [-dl/dz; 0],   H = Qs + G^T D G,  D = lambda / s,
+// (K_sym with d_s = -G d_z and d~_lam = D G d_z eliminated) is solved by
+// projected preconditioned conjugate gradients (Gould, Hribar and Nocedal,
+// 2001) with FP64 vectors, residuals and products (the FP32 inputs are exact
+// in FP64).  Preconditioner and projection: the constraint system
+// [M A^T; A 0] with the FP32 factor stored by the forward (M = its H),
+// applied to the residual scaled to unit max norm.  After every projection
+// the residual loses its A^T v part and v is accumulated into the multiplier
+// (their residual update): the residual of projected CG tends to A^T nu, not
+// to zero, and projecting that large vector in FP32 would leave an error that
+// never shrinks.  Stationary refinement in
+// FP32 stalls once cond(H) eps32 approaches 1; the Krylov iteration only
+// needs the FP32 factor as a preconditioner.  At most 10 * refine_steps
+// iterations; it stops when an update changes d_z by less than 1e-7 relative
+// (about the resolution of the FP32 result).
+struct BwdMixedLayout {
+    int f, y, gz, r4, tp, tp2, gn, scr;                 // FP32, offsets in floats
+    int x, r, gv, d, t1, t2, t3, tm, v, va, scr64, red; // FP64, offsets in doubles from dbase
+    int dbase, end;                                     // bytes
+    __host__ __device__ BwdMixedLayout(int n, int m, int p) {
+        const int N = pad4(n), M = pad4(m), Pp = pad4(p);
+        int o = 0;
+        f = o; o += N; y = o; o += N; gz = o; o += N;
+        r4 = o; o += Pp; tp = o; o += Pp; tp2 = o; o += Pp; gn = o; o += Pp;
+        scr = o; o += 512;
+        dbase = (o * 4 + 15) & ~15;
+        int q = 0;
+        x = q; q += N; r = q; q += N; gv = q; q += N; d = q; q += N;
+        t1 = q; q += N; t2 = q; q += N; t3 = q; q += N;
+        tm = q; q += M; v = q; q += Pp; va = q; q += Pp; scr64 = q; q += 512; red = q; q += 64;
+        end = dbase + q * 8;
+    }
+};
+
+size_t bwd_vec_lds_bytes(int esz, int n, int m, int p) {
+    return esz == 4 ? (size_t)BwdMixedLayout(n, m, p).end : (size_t)BwdLayout(n, m, p).end * esz;
+}
+
+template <int NT>
+__device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int refine_steps) {
+    const int n = P.n, m = P.m, p = P.p;
+    const int tid = threadIdx.x;
+    const BwdMixedLayout Lo(n, m, p);
+    const StateLayout SL = state_layout(4, n, m, p);
+    const float *U = (const float *)(P.state + SL.off_U);
+    const float *Wt = (const float *)(P.state + SL.off_Wt);
+    const float *US = (const float *)(P.state + SL.off_US);
+    const float *__restrict__ Q = P.Q;
+    const float *__restrict__ G = P.G;
+    const float *__restrict__ A = P.A;
+    const float *__restrict__ lam = P.lam;
+    const float *__restrict__ sl = P.s;
+    float *fs = reinterpret_cast<float *>(smem);
+    double *ds = reinterpret_cast<double *>(smem + Lo.dbase);
+    float *f = fs + Lo.f, *y = fs + Lo.y, *gz = fs + Lo.gz, *r4 = fs + Lo.r4, *tp = fs + Lo.tp,
+          *tp2 = fs + Lo.tp2, *gn = fs + Lo.gn, *scr = fs + Lo.scr;
+    double *x = ds + Lo.x, *r = ds + Lo.r, *gv = ds + Lo.gv, *d = ds + Lo.d, *t1 = ds + Lo.t1,
+           *t2 = ds + Lo.t2, *t3 = ds + Lo.t3, *tm = ds + Lo.tm, *v = ds + Lo.v, *va = ds + Lo.va,
+           *scr64 = ds + Lo.scr64, *red = ds + Lo.red;
+
+    // t1 = H w  (FP64)
+    auto h_mv = [&](const double *w) {
+        mv_rows<float, NT, double>(Q, n, n, n, w, t1);
+        mv_rows<float, NT, double>(G, n, m, n, w, tm);
+        colsum_split<float, NT, double>(Q, n, n, n, w, t2, scr64);  // ends with a barrier
+        for (int k = tid; k < m; k += NT) tm[k] *= (double)lam[k] / (double)sl[k];
+        __syncthreads();
+        colsum_split<float, NT, double>(G, n, m, n, tm, t3, scr64);
+        for (int i = tid; i < n; i += NT) t1[i] = 0.5 * (t1[i] + t2[i]) + t3[i];
+        __syncthreads();
+    };
+    // (gv, v): the solution of [M A^T; A 0] [gv; v] = [w; 0] in FP32 on w scaled to unit max norm
+    auto project = [&](double *w) {
+        double *w_upd = w;
+        double mx = 0, d0 = 0, d1 = 0;
+        for (int i = tid; i < n; i += NT) mx = fmax(mx, fabs(w[i]));
+        block_reduce3<double, NT>(d0, mx, d1, red);
+        const double sc = (mx > 0 && isfinite(mx)) ? mx : 0.0;
+        const double inv = sc > 0 ? 1.0 / sc : 0.0;
+        for (int i = tid; i < n; i += NT) f[i] = (float)(w[i] * inv);
+        for (int k = tid; k < p; k += NT) r4[k] = 0.f;
+        __syncthreads();
+        kkt_solve<float, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, gz, gn, scr);
+        for (int i = tid; i < n; i += NT) gv[i] = sc * (double)gz[i];
+        for (int k = tid; k < p; k += NT) v[k] = sc * (double)gn[k];
+        __syncthreads();
+        if (p > 0) {  // residual update: r -= A^T v, multiplier += v
+            colsum_split<float, NT, double>(A, n, p, n, v, t2, scr64);  // ends with a barrier
+            for (int i = tid; i < n; i += NT) w_upd[i] -= t2[i];
+            for (int k = tid; k < p; k += NT) va[k] += v[k];
+            __syncthreads();
+        }
+    };
+    auto dot = [&](const double *a, const double *b) {
+        double acc = 0;
+        for (int i = tid; i < n; i += NT) acc += a[i] * b[i];
+        return block_sum<double, NT>(acc, red);
+    };
+
+    // x = 0, r = H x - (-g) = g, accumulated multiplier va = 0
+    for (int i = tid; i < n; i += NT) { x[i] = 0.0; r[i] = (double)P.g[i]; }
+    for (int k = tid; k < p; k += NT) va[k] = 0.0;
+    __syncthreads();
+    project(r);
+    for (int i = tid; i < n; i += NT) d[i] = -gv[i];
+    __syncthreads();
+    double rg = dot(r, gv);
+    const int max_it = 10 * (refine_steps > 0 ? refine_steps : 1);
+    for (int it = 0; it < max_it && rg > 0 && isfinite(rg); ++it) {
+        h_mv(d);
+        const double dhd = dot(d, t1);
+        if (!(dhd > 0) || !isfinite(dhd)) break;
+        const double alpha = rg / dhd;
+        double upd = 0, nxm = 0, d0 = 0;  // nxm: -max|x| through the min slot
+        for (int i = tid; i < n; i += NT) {
+            const double dx = alpha * d[i];
+            x[i] += dx;
+            r[i] += alpha * t1[i];
+            upd = fmax(upd, fabs(dx));
+            nxm = fmin(nxm, -fabs(x[i]));
+        }
+        block_reduce3<double, NT>(d0, upd, nxm, red);
+        if (upd <= 1e-7 * -nxm) break;
+        project(r);
+        const double rg2 = dot(r, gv);
+        const double beta = rg2 / rg;
+        for (int i = tid; i < n; i += NT) d[i] = -gv[i] + beta * d[i];
+        __syncthreads();
+        rg = rg2;
+    }
+    // r = H x + g - A^T va  ->  0:  H x + A^T (-va) = -g,  so nu = -va
+    // d_s = -G d_z (not stored), d~_lam = D G d_z
+    mv_rows<float, NT, double>(G, n, m, n, x, tm);
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) P.adj[i] = (float)x[i];
+    for (int k = tid; k < m; k += NT) P.adj[n + k] = (float)((double)lam[k] / (double)sl[k] * tm[k]);
+    for (int k = tid; k < p; k += NT) P.adj[n + m + k] = (float)(-va[k]);
+    __syncthreads();
+}
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
@@ -100,6 +239,9 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
     for (int j = blockIdx.x; j < L.count; j += gridDim.x) {
         const BProb<T> P = bwd_problem<T>(L, j);
         if (!P.need) continue;
+        if constexpr (sizeof(T) == 4) {
+            bwd_solve_mixed<NT>(P, smem_raw, L.refine_steps);
+        } else {
         const int n = P.n, m = P.m, p = P.p;
         const BwdLayout Lo(n, m, p);
         const StateLayout SL = state_layout(sizeof(T), n, m, p);
@@ -171,6 +313,7 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         for (int k = tid; k < m; k += NT) P.adj[n + k] = dl[k];
         for (int k = tid; k < p; k += NT) P.adj[n + m + k] = dn[k];
         __syncthreads();
+        }
     }
 }
 

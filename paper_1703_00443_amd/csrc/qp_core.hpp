@@ -155,15 +155,17 @@ __device__ __forceinline__ T row16_sum(T v) {
 // y[r] = sum_{c<cols} M[r][c] x[c]: 16 lanes per row (four rows per wavefront
 // at a time), four loads in flight per lane, in-row DPP reduction.  Measured
 // 3-4x faster than a wavefront per row for global M.  No barrier at the end.
-template <typename T, int NT>
+// V: the vectors' type and the accumulation type (FP64 over an FP32 matrix in
+// the mixed-precision backward).
+template <typename T, int NT, typename V = T>
 __device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int rows, int cols,
-                                        const T *x, T *y) {
+                                        const V *x, V *y) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
     for (int r0 = 4 * w; r0 < rows; r0 += 4 * NW) {
         const int r = r0 + g < rows ? r0 + g : rows - 1;
         const T *row = M + (size_t)r * ld;
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        V a0 = 0, a1 = 0, a2 = 0, a3 = 0;
         int c = cl;
         for (; c + 48 < cols; c += 64) {
             a0 += row[c] * x[c];
@@ -172,7 +174,7 @@ __device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int row
             a3 += row[c + 48] * x[c + 48];
         }
         for (; c < cols; c += 16) a0 += row[c] * x[c];
-        const T s = row16_sum((a0 + a1) + (a2 + a3));
+        const V s = row16_sum((a0 + a1) + (a2 + a3));
         if (cl == 0 && r0 + g < rows) y[r0 + g] = s;
     }
 }
@@ -180,15 +182,15 @@ __device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int row
 // out[i] = sum_{k<rows} M[k][i] v[k] for i < cols.  When cols < NT the rows
 // are split into up to eight groups whose partial sums (scratch, NT entries)
 // are added in a fixed order; otherwise one thread per column.
-template <typename T, int NT>
-__device__ __forceinline__ void colsum_split(const T *M, int ld, int rows, int cols, const T *v, T *out,
-                                             T *scratch) {
+template <typename T, int NT, typename V = T>
+__device__ __forceinline__ void colsum_split(const T *M, int ld, int rows, int cols, const V *v, V *out,
+                                             V *scratch) {
     const int ng = cols > 0 ? max(1, min(NT / cols, 8)) : 1;
     const int chunk = (rows + ng - 1) / ng;
     for (int t = threadIdx.x; t < ng * cols; t += NT) {
         const int q = t / cols, i = t - q * cols;
         const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0;
+        V a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0;
         int k = k0;
         for (; k + 7 < k1; k += 8) {
             a0 += M[(size_t)k * ld + i] * v[k];
@@ -201,14 +203,14 @@ __device__ __forceinline__ void colsum_split(const T *M, int ld, int rows, int c
             a7 += M[(size_t)(k + 7) * ld + i] * v[k + 7];
         }
         for (; k < k1; ++k) a0 += M[(size_t)k * ld + i] * v[k];
-        const T r = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+        const V r = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
         if (ng == 1) out[i] = r;
         else scratch[t] = r;
     }
     if (ng > 1) {
         __syncthreads();
         for (int i = threadIdx.x; i < cols; i += NT) {
-            T acc = scratch[i];
+            V acc = scratch[i];
             for (int q = 1; q < ng; ++q) acc += scratch[q * cols + i];
             out[i] = acc;
         }

@@ -133,11 +133,11 @@ def test_uneven_4096_stratified_256_vs_oracle():
       * z against the oracle replaying the GPU's iteration count;
       * every gradient against the oracle's backward (eq. grads) at the iterate the
         GPU returned, with h' = G z + s so that its system is the paper's K_sym of
-        that iterate, wherever the reduced matrix H = Qs + G^T D G there has
-        kappa(H) * eps32 <= 1.  Beyond that bound FP32 rounding alone allows
-        relative errors of order one in the solve, and the gradient itself moves
-        by more than the tolerance under perturbations of z at FP32 resolution;
-        those problems (14% of this sample) are counted, not compared."""
+        that iterate.  The FP32 trajectory itself drifts from the FP64 replay, and
+        near constraints with both a small slack and a small multiplier the
+        gradient amplifies that drift past the tolerance; at a given iterate the
+        backward is well defined, and 37 of these 256 iterates have
+        cond(H) eps32 > 1, which the backward's FP64 projected CG must handle."""
     import os
     from concurrent.futures import ThreadPoolExecutor
     import torch
@@ -153,7 +153,6 @@ def test_uneven_4096_stratified_256_vs_oracle():
     sample = [int(i) for i in order[::16]]
     assert len(sample) == 256
     res = {i: vb.result(i) for i in sample}
-    eps32 = float(np.finfo(np.float32).eps)
     c = lambda x: None if x is None else np.asarray(x, dtype=np.float32).astype(np.float64)
 
     def check(i):
@@ -162,22 +161,12 @@ def test_uneven_4096_stratified_256_vs_oracle():
         ez = z_err(r["z"], ref["z"])
         Q, A, G, g = c(P["Q"]), c(P.get("A")), c(P.get("G")), c(P["g"])
         z, lam, nu, s = (r[k].astype(np.float64) for k in ("z", "lam", "nu", "s"))
-        H = (Q + Q.T) / 2 + G.T @ ((lam / s)[:, None] * G)
-        ev = np.linalg.eigvalsh(H)
-        kappa = ev[-1] / ev[0] if ev[0] > 0 else np.inf
-        if kappa * eps32 > 1.0:
-            return i, ez, None
         go = oracle.backward(Q, A, G, G @ z + s, z, lam, nu, g)
         sc = grad_scale(go)
         eg = max(g_err(r[k], go[k], sc) for k in ("dQ", "dq", "dA", "db", "dG", "dh"))
         return i, ez, eg
 
-    skipped = 0
     with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
         for i, ez, eg in ex.map(check, sample):
             assert ez <= TOL_Z[np.float32], (i, dims[i], ez)
-            if eg is None:
-                skipped += 1
-            else:
-                assert eg <= TOL_G[np.float32], (i, dims[i], eg)
-    assert skipped <= 256 // 5, skipped  # 37 of 256 measured on this workload
+            assert eg <= TOL_G[np.float32], (i, dims[i], eg)
