@@ -174,7 +174,8 @@ int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_d
     qp_workspace_query(dtype, batch, d, opts, nullptr, &need);
     if (ws_bytes < need || (need > 0 && !ws)) return QP_EWS;
     const int esz = esize(dtype);
-    if (bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq) > (size_t)device_lds_limit()) return QP_ETOOBIG;
+    const int lim = device_lds_limit();
+    if (bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim) > (size_t)lim) return QP_ETOOBIG;
 
     BwdLaunch L;
     memset(&L, 0, sizeof(L));
@@ -190,7 +191,8 @@ int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_d
     L.adj = ws;
     L.adj_stride = adj_stride_elems(d.nz, d.nineq, d.neq);
     L.refine_steps = opts->refine_steps;
-    L.lds_bytes = (int)bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq);
+    L.lds_bytes = (int)bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim);
+    L.lds_limit = lim;
     L.max_rows = d.nz + d.nineq + d.neq + 1;
     return hip_ret(launch_backward(dtype, L, (hipStream_t)stream));
 }
@@ -287,10 +289,12 @@ int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc 
     const int esz = esize(dtype);
     int lds = 0, rows = 0;
     size_t stride = 0;
+    const int lim = device_lds_limit();
     for (int i = 0; i < count; ++i) {
         const qp_problem_desc &d = desc_host[i];
-        if (bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq) > (size_t)device_lds_limit()) return QP_ETOOBIG;
-        lds = std::max(lds, (int)bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq));
+        const size_t b = bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim);
+        if (b > (size_t)lim) return QP_ETOOBIG;
+        lds = std::max(lds, (int)b);
         rows = std::max(rows, d.nz + d.nineq + d.neq + 1);
         stride = std::max(stride, adj_stride_elems(d.nz, d.nineq, d.neq));
     }
@@ -308,6 +312,7 @@ int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc 
     L.adj_stride = stride;
     L.refine_steps = opts->refine_steps;
     L.lds_bytes = lds;
+    L.lds_limit = lim;
     L.max_rows = rows;
     return hip_ret(launch_backward(dtype, L, (hipStream_t)stream));
 }

@@ -106,16 +106,21 @@ struct BwdLayout {
 // needs the FP32 factor as a preconditioner.  At most 10 * refine_steps
 // iterations; it stops when an update changes d_z by less than 1e-7 relative
 // (about the resolution of the FP32 result).
+// With `stage`, Q, G and A are copied to LDS once (the iteration reads them
+// four times per step); the choice depends on the problem's dims and the
+// device LDS size only, and the products run the same code on either copy.
 struct BwdMixedLayout {
-    int f, y, gz, r4, tp, tp2, gn, scr;                 // FP32, offsets in floats
+    int f, y, gz, r4, tp, tp2, gn, scr, qs, gs, as;     // FP32, offsets in floats
     int x, r, gv, d, t1, t2, t3, tm, v, va, scr64, red; // FP64, offsets in doubles from dbase
     int dbase, end;                                     // bytes
-    __host__ __device__ BwdMixedLayout(int n, int m, int p) {
+    __host__ __device__ BwdMixedLayout(int n, int m, int p, bool stage) {
         const int N = pad4(n), M = pad4(m), Pp = pad4(p);
         int o = 0;
         f = o; o += N; y = o; o += N; gz = o; o += N;
         r4 = o; o += Pp; tp = o; o += Pp; tp2 = o; o += Pp; gn = o; o += Pp;
         scr = o; o += 512;
+        qs = gs = as = 0;
+        if (stage) { qs = o; o += n * n; gs = o; o += m * n; as = o; o += p * n; }
         dbase = (o * 4 + 15) & ~15;
         int q = 0;
         x = q; q += N; r = q; q += N; gv = q; q += N; d = q; q += N;
@@ -125,25 +130,36 @@ struct BwdMixedLayout {
     }
 };
 
-size_t bwd_vec_lds_bytes(int esz, int n, int m, int p) {
-    return esz == 4 ? (size_t)BwdMixedLayout(n, m, p).end : (size_t)BwdLayout(n, m, p).end * esz;
+__host__ __device__ inline bool bwd_mixed_stage(int n, int m, int p, int lds_limit) {
+    return BwdMixedLayout(n, m, p, true).end <= lds_limit;
 }
 
-template <int NT>
+size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit) {
+    return esz == 4 ? (size_t)BwdMixedLayout(n, m, p, bwd_mixed_stage(n, m, p, lds_limit)).end
+                    : (size_t)BwdLayout(n, m, p).end * esz;
+}
+
+template <int NT, bool STAGE>
 __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int refine_steps) {
     const int n = P.n, m = P.m, p = P.p;
     const int tid = threadIdx.x;
-    const BwdMixedLayout Lo(n, m, p);
+    const BwdMixedLayout Lo(n, m, p, STAGE);
     const StateLayout SL = state_layout(4, n, m, p);
     const float *U = (const float *)(P.state + SL.off_U);
     const float *Wt = (const float *)(P.state + SL.off_Wt);
     const float *US = (const float *)(P.state + SL.off_US);
-    const float *__restrict__ Q = P.Q;
-    const float *__restrict__ G = P.G;
-    const float *__restrict__ A = P.A;
     const float *__restrict__ lam = P.lam;
     const float *__restrict__ sl = P.s;
     float *fs = reinterpret_cast<float *>(smem);
+    const float *Q = P.Q, *G = P.G, *A = P.A;
+    if constexpr (STAGE) {
+        float *qs = fs + Lo.qs, *gs = fs + Lo.gs, *as = fs + Lo.as;
+        for (int e = tid; e < n * n; e += NT) qs[e] = P.Q[e];
+        for (int e = tid; e < m * n; e += NT) gs[e] = P.G[e];
+        for (int e = tid; e < p * n; e += NT) as[e] = P.A[e];
+        __syncthreads();
+        Q = qs; G = gs; A = as;
+    }
     double *ds = reinterpret_cast<double *>(smem + Lo.dbase);
     float *f = fs + Lo.f, *y = fs + Lo.y, *gz = fs + Lo.gz, *r4 = fs + Lo.r4, *tp = fs + Lo.tp,
           *tp2 = fs + Lo.tp2, *gn = fs + Lo.gn, *scr = fs + Lo.scr;
@@ -240,7 +256,10 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         const BProb<T> P = bwd_problem<T>(L, j);
         if (!P.need) continue;
         if constexpr (sizeof(T) == 4) {
-            bwd_solve_mixed<NT>(P, smem_raw, L.refine_steps);
+            if (bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit))
+                bwd_solve_mixed<NT, true>(P, smem_raw, L.refine_steps);
+            else
+                bwd_solve_mixed<NT, false>(P, smem_raw, L.refine_steps);
         } else {
         const int n = P.n, m = P.m, p = P.p;
         const BwdLayout Lo(n, m, p);

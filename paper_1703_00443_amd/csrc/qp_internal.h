@@ -82,6 +82,7 @@ struct BwdLaunch {
     size_t adj_stride;        // elements per problem
     int refine_steps;
     int lds_bytes;
+    int lds_limit;            // device LDS per workgroup (per-problem plans depend on it only)
     int max_rows;             // largest nz + nineq + neq + 1 of the launch
 };
 
@@ -96,8 +97,9 @@ int fwd_plan(int esz, int n, int m, int p, int variant, int lds_limit, int *lds_
 // Workgroups of the forward kernel that fit on the device at once with this LDS.
 int fwd_resident_workgroups(qp_dtype dt, int lds_bytes);
 
-// Dynamic LDS bytes a problem's vectors need in the backward kernel.
-size_t bwd_vec_lds_bytes(int esz, int n, int m, int p);
+// Dynamic LDS bytes a problem needs in the backward kernel on a device with
+// `lds_limit` bytes per workgroup (FP32 stages Q, G and A there when they fit).
+size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit);
 
 hipError_t launch_forward(qp_dtype dt, const FwdLaunch &L, hipStream_t st);
 hipError_t launch_backward(qp_dtype dt, const BwdLaunch &L, hipStream_t st);
