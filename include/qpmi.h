@@ -82,8 +82,20 @@ typedef struct {
     double tol;           /* stop when max(mu, |r_x|inf, |r_s|inf, |r_y|inf) <= tol,
                              mu = s^T lambda / nineq (default 1e-8 F64, 1e-3 F32)        */
     int32_t variant;      /* kernel variant: 0 = pick automatically, else a QP_VARIANT_* */
-    uint32_t flags;       /* reserved, must be 0                                         */
+    uint32_t flags;       /* QP_FLAG_* bits (others must be 0)                           */
 } qp_opts;
+
+/* Flags of qp_opts.flags.
+ * QP_FLAG_G_UNIT_ROWS: every row of G is a signed unit vector (one entry +1 or
+ *   -1, the rest 0), as for bounds z_j <= h_k or -z_j <= h_k (the box and
+ *   non-negativity layers of Section 4).  G is still passed densely.  The
+ *   register-tile policy then forms G^T D G as a diagonal and applies G by
+ *   gathers instead of products; a problem whose G does not have the structure
+ *   (checked in the kernel) is solved by the dense path.  Results equal the
+ *   dense path's up to rounding.  Used by qp_forward_batched for problems the
+ *   register-tile policy takes; elsewhere, and in qp_forward_varlen, the flag is
+ *   accepted and the dense path runs.  The backward is unchanged. */
+enum { QP_FLAG_G_UNIT_ROWS = 1u };
 
 enum {
     QP_VARIANT_AUTO = 0,

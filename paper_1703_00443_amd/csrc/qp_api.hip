@@ -90,7 +90,7 @@ int32_t qp_workspace_query(qp_dtype dtype, int32_t batch, qp_dims d, const qp_op
 static int32_t check_opts(const qp_opts *o) {
     if (!o) return QP_EARG;
     if (o->max_iter < 0 || o->max_iter > 100000 || o->refine_steps < 0 || o->refine_steps > 100 ||
-        !(o->tol >= 0.0) || o->flags != 0 || o->variant < 0 || o->variant > QP_VARIANT_STREAM)
+        !(o->tol >= 0.0) || (o->flags & ~(uint32_t)QP_FLAG_G_UNIT_ROWS) != 0 || o->variant < 0 || o->variant > QP_VARIANT_STREAM)
         return QP_EARG;
     return QP_OK;
 }
@@ -152,6 +152,7 @@ int32_t qp_forward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_da
     L.lds_bytes = lds;
     L.lds_limit = lim;
     L.variant = opts->variant;
+    L.flags = opts->flags;
     return hip_ret(launch_forward(dtype, L, (hipStream_t)stream));
 }
 
@@ -263,6 +264,7 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
     L.lds_bytes = lds;
     L.lds_limit = lim;
     L.variant = opts->variant;
+    L.flags = opts->flags;
     L.queue = (int *)ws;
     L.grid = std::min(count, fwd_resident_workgroups(dtype, lds));
     return hip_ret(launch_forward(dtype, L, (hipStream_t)stream));

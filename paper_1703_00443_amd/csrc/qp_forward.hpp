@@ -133,12 +133,20 @@ static hipError_t launch_uniform(const FwdLaunch &L, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename T, bool EQ, bool UNIT>
+static hipError_t launch_uniform_tiled_u(int pol, const FwdLaunch &L, hipStream_t st) {
+    if (pol == kPolicyTiledGLds) return launch_uniform<T, TiledFactor<T, true, 8, EQ, UNIT>>(L, st);
+    if (pol == kPolicyTiledGGlobal) return launch_uniform<T, TiledFactor<T, false, 8, EQ, UNIT>>(L, st);
+    if constexpr (sizeof(T) == 4) return launch_uniform<T, TiledFactor<T, false, 16, EQ, UNIT>>(L, st);
+    return hipErrorInvalidValue;
+}
+
+// QP_FLAG_G_UNIT_ROWS selects the unit-row instantiation (uniform batches; the
+// uneven-batch kernel runs the dense path for every problem).
 template <typename T, bool EQ>
 static hipError_t launch_uniform_tiled(int pol, const FwdLaunch &L, hipStream_t st) {
-    if (pol == kPolicyTiledGLds) return launch_uniform<T, TiledFactor<T, true, 8, EQ>>(L, st);
-    if (pol == kPolicyTiledGGlobal) return launch_uniform<T, TiledFactor<T, false, 8, EQ>>(L, st);
-    if constexpr (sizeof(T) == 4) return launch_uniform<T, TiledFactor<T, false, 16, EQ>>(L, st);
-    return hipErrorInvalidValue;
+    if ((L.flags & QP_FLAG_G_UNIT_ROWS) && L.nineq > 0) return launch_uniform_tiled_u<T, EQ, true>(pol, L, st);
+    return launch_uniform_tiled_u<T, EQ, false>(pol, L, st);
 }
 
 __global__ void qp_zero_counter_kernel(int *c);

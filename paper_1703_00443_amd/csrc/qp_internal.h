@@ -58,6 +58,7 @@ struct FwdLaunch {
     int lds_bytes;                         // dynamic LDS of the launch (max over its problems)
     int lds_limit;                         // device LDS per workgroup (plans depend on it only)
     int variant;                           // QP_VARIANT_* requested (0 = per-problem plan)
+    unsigned flags;                        // QP_FLAG_* of the call
     int *queue;                            // varlen: work counter (zeroed by the launch), else null
     int grid;                              // workgroups launched (0 = one per problem)
 };

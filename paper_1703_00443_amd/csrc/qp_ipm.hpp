@@ -32,12 +32,14 @@ struct Prob {
     int out;        // index into status / iters
     int variant;    // requested variant (QP_VARIANT_*)
     int lds_limit;  // device LDS per workgroup (the streamed policy sizes its chunks by it)
+    unsigned flags; // QP_FLAG_* of the call
 };
 
 template <typename T>
 __device__ __forceinline__ Prob<T> fwd_problem(const FwdLaunch &L, int idx) {
     Prob<T> P;
     P.lds_limit = L.lds_limit;
+    P.flags = L.flags;
     if (L.desc == nullptr) {
         const int j = idx;
         P.n = L.nz; P.m = L.nineq; P.p = L.neq;

@@ -273,7 +273,9 @@ struct TileMap {
 
 // EQ: the problem has equality rows (Schur complement on A).  Instantiated
 // separately so that the no-equality solve carries none of that code.
-template <typename T, bool GL, int NTL, bool EQ>
+// UNIT: the call set QP_FLAG_G_UNIT_ROWS; a separate instantiation, so that the
+// dense kernels carry none of the unit-row code.
+template <typename T, bool GL, int NTL, bool EQ, bool UNIT = false>
 struct TiledFactor {
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr int NS = TileMap<NTL>::NS;
@@ -285,6 +287,12 @@ struct TiledFactor {
     T *part, *yv, *xv, *panel, *scratch, *S, *xdp, *pv1, *pv2;
     int *flag;
     int w, lane, g, c;
+    // rows of G that are signed unit vectors (QP_FLAG_G_UNIT_ROWS): row k has
+    // its one entry usign[k] in column ucol[k]; the rows of column j, in
+    // order, are urow[uoff[j] .. uoff[j+1]).  All live in the G region.
+    bool unit;
+    int *ucol, *uoff, *urow;
+    T *usign;
     v4 sq[NS];
 
     __device__ __forceinline__ int trow(int s) const { return TileMap<NTL>::row(s); }
@@ -311,6 +319,12 @@ struct TiledFactor {
         flag = reinterpret_cast<int *>(sm + L.flag);
         G = sm + L.G; ldg = np + 1; lds = h_ld(p); ldu = u_ld(n);
         lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
+        const int gcap = (GL ? ((m + 3) & ~3) : kGChunk) * (np + 1);
+        unit = UNIT && (P.flags & QP_FLAG_G_UNIT_ROWS) != 0 && m > 0 && 3 * m + n + 1 <= gcap;
+        usign = sm + L.G;
+        ucol = reinterpret_cast<int *>(sm + L.G + m);
+        uoff = ucol + m;
+        urow = uoff + n + 1;
     }
 
     // Rows [k0, k0 + rows) of G into the LDS buffer, zero-padded to whole MFMA
@@ -329,12 +343,48 @@ struct TiledFactor {
     // loads in form() and qs_mv().  With equality rows the Schur step stores U there every
     // factorization, and Qs is taken from Q itself.
     __device__ __forceinline__ void prepare() {
+        if (UNIT && unit) {
+            // find each row's one entry; any other row sends the problem down the dense path
+            T bad = 0, d0 = 0, d1 = 0;
+            for (int k = threadIdx.x; k < m; k += NT) {
+                int col = 0, cnt = 0;
+                T val = 0;
+                for (int j = 0; j < n; ++j) {
+                    const T v = Gsrc[(size_t)k * n + j];
+                    if (v != T(0)) { ++cnt; col = j; val = v; }
+                }
+                if (cnt != 1 || !(val == T(1) || val == T(-1))) bad = 1;
+                ucol[k] = col;
+                usign[k] = val;
+            }
+            block_reduce3<T, NT>(bad, d0, d1, scratch);
+            unit = bad == T(0);
+            if (unit) {
+                // rows per column, offsets (one thread; n is small), rows in order
+                for (int j = threadIdx.x; j < n; j += NT) {
+                    int cnt = 0;
+                    for (int k = 0; k < m; ++k) cnt += ucol[k] == j;
+                    uoff[j + 1] = cnt;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    uoff[0] = 0;
+                    for (int j = 0; j < n; ++j) uoff[j + 1] += uoff[j];
+                }
+                __syncthreads();
+                for (int j = threadIdx.x; j < n; j += NT) {
+                    int o = uoff[j];
+                    for (int k = 0; k < m; ++k)
+                        if (ucol[k] == j) urow[o++] = k;
+                }
+            }
+        }
         if (!EQ)
             for (int e = threadIdx.x; e < n * n; e += NT) {
                 const int i = e / n, j = e - i * n;
                 Ust[e] = T(0.5) * (Q[(size_t)i * n + j] + Q[(size_t)j * n + i]);
             }
-        if (GL) stage_g(0, m);
+        if (GL && !(UNIT && unit)) stage_g(0, m);
         __syncthreads();
     }
 
@@ -343,6 +393,15 @@ struct TiledFactor {
     // k loop runs outside the tile loop so that the MFMAs of the tiles of a
     // wavefront are independent and overlap their operand loads.
     __device__ __forceinline__ void form(const T *D) {
+        if (UNIT && unit) {
+            // G^T D G is diagonal: column j sums D over its rows, in row order
+            for (int j = threadIdx.x; j < n; j += NT) {
+                T a = 0;
+                for (int t = uoff[j]; t < uoff[j + 1]; ++t) a += D[urow[t]];
+                xv[j] = a;
+            }
+            __syncthreads();
+        }
         lane_ids();
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -361,12 +420,13 @@ struct TiledFactor {
                         const T qb = Q[in ? (size_t)col * n + row : 0];
                         qs = T(0.5) * (qa + qb);
                     }
+                    if (UNIT && unit && in && row == col) qs += xv[row];
                     acc[r] = in ? qs : (row == col ? T(1) : T(0));
                 }
             }
             sq[s] = acc;
         }
-        for (int k0 = 0; k0 < m; k0 += (GL ? m : kGChunk)) {
+        for (int k0 = 0; k0 < ((UNIT && unit) ? 0 : m); k0 += (GL ? m : kGChunk)) {
             const int rows = GL ? m : min(kGChunk, m - k0);
             if (!GL) {
                 __syncthreads();  // previous chunk consumed
@@ -678,10 +738,27 @@ struct TiledFactor {
         rowdot_split<T, NT>(M, ld, rows, cols, x, out, scratch);
     }
     __device__ __forceinline__ void gt_mv(const T *v, T *out) {
+        if (UNIT && unit) {
+            for (int j = threadIdx.x; j < n; j += NT) {
+                T a = 0;
+                for (int t = uoff[j]; t < uoff[j + 1]; ++t) {
+                    const int k = urow[t];
+                    a += usign[k] * v[k];
+                }
+                out[j] = a;
+            }
+            __syncthreads();
+            return;
+        }
         if (GL) colsum(G, ldg, m, n, v, out);
         else colsum(Gsrc, n, m, n, v, out);
     }
     __device__ __forceinline__ void g_mv(const T *x, T *out) {
+        if (UNIT && unit) {
+            for (int k = threadIdx.x; k < m; k += NT) out[k] = usign[k] * x[ucol[k]];
+            __syncthreads();
+            return;
+        }
         if (GL) {
             rowdot(G, ldg, m, n, x, out);
         } else {

@@ -72,6 +72,29 @@ def make_batch(seed: int, B: int, n: int, m: int, p: int, row_normalize: bool = 
     return QPBatch(*arrs).astype(dtype)
 
 
+def box_batch(seed: int, B: int, n: int, dtype=np.float64) -> QPBatch:
+    """Box-constrained QPs l <= z <= u (the bound constraints of the paper's
+    box and ReLU layers, Section 4): G = [I; -I], h = [u; -l] with
+    u ~ U(0.5, 1.5), l ~ -U(0.5, 1.5); Q, q and dl/dz as above (q scaled by 3
+    so that a good share of the bounds is active).  Problem i uses
+    default_rng([seed, i])."""
+    I = np.eye(n)
+    G = np.concatenate([I, -I])
+    parts = []
+    for i in range(B):
+        rng = np.random.default_rng([seed, i])
+        L = rng.standard_normal((n, n))
+        Q = L @ L.T / n + 1e-3 * np.eye(n)
+        q = 3.0 * rng.standard_normal(n)
+        u = rng.uniform(0.5, 1.5, n)
+        lo = -rng.uniform(0.5, 1.5, n)
+        g = rng.standard_normal(n)
+        parts.append((Q, q, np.concatenate([u, -lo]), g))
+    return QPBatch(np.stack([x[0] for x in parts]), np.stack([x[1] for x in parts]),
+                   np.zeros((B, 0, n)), np.zeros((B, 0)), np.broadcast_to(G, (B, 2 * n, n)).copy(),
+                   np.stack([x[2] for x in parts]), np.stack([x[3] for x in parts])).astype(dtype)
+
+
 # Workload shapes (sizes from the paper's timing experiment and its extensions).
 CPU_CHECK = dict(seed=1000, B=8, n=10, m=20, p=5, row_normalize=False)
 PAPER_SCALE = dict(seed=1001, B=128, n=100, m=100, p=0, row_normalize=True)

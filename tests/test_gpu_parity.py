@@ -230,3 +230,35 @@ def test_automatic_plan_by_size():
         assert qb.plan(tdt, 300, 300, 20)[0] == qb.VARIANT_STREAM
     assert qb.plan(torch.float32, 250, 400, 10)[0] == qb.VARIANT_TILED
     assert qb.plan(torch.float64, 250, 400, 10)[0] == qb.VARIANT_STREAM
+
+
+@pytest.mark.parametrize("n", [10, 60, 100, 200])
+def test_unit_row_flag_box_qp(n):
+    """QP_FLAG_G_UNIT_ROWS on box QPs (G = [I; -I]): the register-tile policy forms
+    G^T D G as a diagonal and applies G by gathers.  Against the oracle replay in
+    both precisions (nz = 200 runs only in FP32, the other sizes where the
+    register tiles take them), and close to the dense path's result."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    b = synth.box_batch(seed=2024 + n, B=3, n=n)
+    for dtype in ((np.float32,) if n > 128 else (np.float64, np.float32)):
+        tdt = torch.float64 if dtype == np.float64 else torch.float32
+        assert qb.plan(tdt, n, 2 * n, 0)[0] == qb.VARIANT_TILED
+        fast = _run(b, dtype, opts_over={"flags": qb.FLAG_G_UNIT_ROWS})
+        dense = _run(b, dtype)
+        _check(b, fast, dtype, range(3))
+        for i in range(3):
+            if fast["iters"][i] == dense["iters"][i]:
+                assert z_err(fast["z"][i], dense["z"][i]) <= TOL_Z[dtype]
+
+
+def test_unit_row_flag_falls_back_on_dense_g():
+    """With the flag set but a G whose rows are not signed unit vectors, the
+    kernel takes the dense path: bitwise the unflagged result."""
+    from paper_1703_00443_amd import binding as qb
+    b = synth.make_batch(seed=77, B=3, n=40, m=80, p=4, row_normalize=True)
+    for dtype in (np.float64, np.float32):
+        a = _run(b, dtype, opts_over={"flags": qb.FLAG_G_UNIT_ROWS})
+        d = _run(b, dtype)
+        for k in ("z", "lam", "nu", "s", "iters", "dQ", "dG"):
+            np.testing.assert_array_equal(a[k], d[k], err_msg=k)
