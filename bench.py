@@ -279,6 +279,42 @@ def time_uniform(B, n, m, p, dtype, steps, warmup=2, seed=1100, serial=False):
     return out
 
 
+def time_box(n, dtype, steps, B=128, seed=5):
+    """Forward milliseconds of a batch of box QPs (G = [I; -I]) without and with
+    QP_FLAG_G_UNIT_ROWS, and the backward, HIP events on the launch stream."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd import synth
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    b = synth.box_batch(seed=seed, B=B, n=n)
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(npdt))).to(dev)
+    prob = qb.make_problem(T(b.Q), T(b.q), None, None, T(b.G), T(b.h))
+    g = T(b.g)
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, flag in (("dense", 0), ("unit_rows", qb.FLAG_G_UNIT_ROWS)):
+        opts = qb.default_opts(tdt, flags=flag)
+        fw = qb.forward(prob, opts)
+        for _ in range(2):
+            qb.forward(prob, opts, out=fw)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        for k in range(steps):
+            ev[k][0].record(stream)
+            qb.forward(prob, opts, out=fw)
+            ev[k][1].record(stream)
+            qb.backward(prob, fw, g, opts)
+            ev[k][2].record(stream)
+        torch.cuda.synchronize()
+        out[name + "_fwd_ms"] = round(float(np.mean([a.elapsed_time(c) for a, c, _ in ev])), 4)
+        out[name + "_bwd_ms"] = round(float(np.mean([c.elapsed_time(d) for _, c, d in ev])), 4)
+        out[name + "_iters_mean"] = round(float(fw.iters.float().mean().item()), 3)
+    out["fwd_speedup"] = round(out["dense_fwd_ms"] / out["unit_rows_fwd_ms"], 3)
+    return out
+
+
 def bench_sweep(args):
     """The two solver-timing experiments of Section 5.1 as extra rows: (1) a
     batch of 128 QPs with nz = nineq in {10, 50, 100, 500}, forward and backward
@@ -299,12 +335,20 @@ def bench_sweep(args):
                 r["serial_solves_per_s"] = round(B / (r["serial_ms"] * 1e-3), 1)
             rows_batch.append({"dtype": dt, "batch": B, "nz": 100, "nineq": 100, **r})
             print("sweep batch %s B=%d: %s" % (dt, B, r), file=sys.stderr, flush=True)
+    rows_box = []
+    for dt in dts:
+        for n in (60, 100) + ((200,) if dt == "f32" else ()):
+            r = time_box(n, dt, steps)
+            rows_box.append({"dtype": dt, "batch": 128, "nz": n, "nineq": 2 * n, **r})
+            print("sweep box %s nz=%d: %s" % (dt, n, r), file=sys.stderr, flush=True)
     return {"metric": "QP layer time vs size and vs batch (paper's solver-timing experiments)",
             "unit": "ms per call", "n_gpus": 1, "steps": steps, "higher_is_better": False,
             "data": "synthetic (seeded generator of the paper's timing experiment, row-normalised G)",
             "config": {"workload": "sizes nz=nineq in {10,50,100,500} at batch 128; batch sizes "
-                                   "1..2048 at nz=nineq=100; neq=0; fwd and bwd timed apart"},
-            "size_sweep": rows_size, "batch_sweep": rows_batch}
+                                   "1..2048 at nz=nineq=100; neq=0; fwd and bwd timed apart; "
+                                   "box QPs (G = [I; -I]) at batch 128 with and without "
+                                   "QP_FLAG_G_UNIT_ROWS"},
+            "size_sweep": rows_size, "batch_sweep": rows_batch, "box_qp": rows_box}
 
 
 def main():
