@@ -104,8 +104,9 @@ struct BwdLayout {
 // never shrinks.  Stationary refinement in
 // FP32 stalls once cond(H) eps32 approaches 1; the Krylov iteration only
 // needs the FP32 factor as a preconditioner.  At most 10 * refine_steps
-// iterations; it stops when an update changes d_z by less than 1e-7 relative
-// (about the resolution of the FP32 result).
+// iterations; it stops when a correction of d_z, or the next one predicted
+// from the rate of the last two, is below 1e-7 relative (about the resolution
+// of the FP32 result).
 // With `stage`, Q, G and A are copied to LDS once (the iteration reads them
 // four times per step); the choice depends on the problem's dims and the
 // device LDS size only, and the products run the same code on either copy.
@@ -167,7 +168,7 @@ __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int 
            *t2 = ds + Lo.t2, *t3 = ds + Lo.t3, *tm = ds + Lo.tm, *v = ds + Lo.v, *va = ds + Lo.va,
            *scr64 = ds + Lo.scr64, *red = ds + Lo.red;
 
-    // t1 = H w  (FP64)
+    // t1 = H w  (FP64); returns w^T H w
     auto h_mv = [&](const double *w) {
         mv_rows<float, NT, double>(Q, n, n, n, w, t1);
         mv_rows<float, NT, double>(G, n, m, n, w, tm);
@@ -175,8 +176,13 @@ __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int 
         for (int k = tid; k < m; k += NT) tm[k] *= (double)lam[k] / (double)sl[k];
         __syncthreads();
         colsum_split<float, NT, double>(G, n, m, n, tm, t3, scr64);
-        for (int i = tid; i < n; i += NT) t1[i] = 0.5 * (t1[i] + t2[i]) + t3[i];
-        __syncthreads();
+        double acc = 0;
+        for (int i = tid; i < n; i += NT) {
+            const double h = 0.5 * (t1[i] + t2[i]) + t3[i];
+            t1[i] = h;
+            acc += w[i] * h;
+        }
+        return block_sum<double, NT>(acc, red);  // its barriers also publish t1
     };
     // (gv, v): the solution of [M A^T; A 0] [gv; v] = [w; 0] in FP32 on w scaled to unit max norm
     auto project = [&](double *w) {
@@ -215,9 +221,9 @@ __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int 
     __syncthreads();
     double rg = dot(r, gv);
     const int max_it = 10 * (refine_steps > 0 ? refine_steps : 1);
+    double prev_upd = 0;
     for (int it = 0; it < max_it && rg > 0 && isfinite(rg); ++it) {
-        h_mv(d);
-        const double dhd = dot(d, t1);
+        const double dhd = h_mv(d);
         if (!(dhd > 0) || !isfinite(dhd)) break;
         const double alpha = rg / dhd;
         double upd = 0, nxm = 0, d0 = 0;  // nxm: -max|x| through the min slot
@@ -229,7 +235,11 @@ __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int 
             nxm = fmin(nxm, -fabs(x[i]));
         }
         block_reduce3<double, NT>(d0, upd, nxm, red);
-        if (upd <= 1e-7 * -nxm) break;
+        // converged: this correction, or the next one predicted from the rate of
+        // the last two, below 1e-7 of d_z
+        const double tolx = 1e-7 * -nxm;
+        if (upd <= tolx || (prev_upd > 0 && upd * (upd / prev_upd) <= tolx)) break;
+        prev_upd = upd;
         project(r);
         const double rg2 = dot(r, gv);
         const double beta = rg2 / rg;
