@@ -135,6 +135,17 @@ def bench_uneven(args):
     st = vb.status[:count].cpu().numpy()
     it = vb.iters[:count].cpu().numpy()
     flops = sum(algorithmic_flops(n, m, p, [k]) for (n, m, p), k in zip(dims, it))
+    # the forward kernel alone (HIP events on the launch stream), for the roofline
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(max(1, args.steps))]
+    for a, b in evs:
+        a.record(stream)
+        vb.forward()
+        b.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    fwd_tf = flops / (fwd_ms * 1e-3) / 1e12
     # per size bucket: the bucket's problems alone, one launch each (forward + backward)
     buckets = []
     edges = (8, 32, 64, 128, 192, 256)
@@ -161,6 +172,10 @@ def bench_uneven(args):
                                             "neq~U{0..nz/4}, one persistent launch, graph-captured"
                                             % count},
             "fwd_algorithmic_tflops": round(flops / el / 1e12, 3), "per_bucket": buckets,
+            "roofline": {"kernel": "qp_forward_varlen_kernel", "bound": "mfma", "achieved": round(fwd_tf, 4),
+                         "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                         "frac": round(fwd_tf / PEAK_TFLOPS["f32"], 5), "traffic": None,
+                         "flops_per_launch": flops, "launch_ms": round(fwd_ms, 4)},
             "status_counts": np.bincount(st, minlength=5).tolist(), "iters_mean": float(it.mean())}
 
 
