@@ -143,3 +143,26 @@ def test_product_path_refuses_cpu_tensors():
     binding, _ = _lib()
     with pytest.raises(RuntimeError):
         binding.make_problem(torch.eye(3, dtype=torch.float64), torch.zeros(3, dtype=torch.float64))
+
+
+def test_plan_query_host_side():
+    """qp_plan: argument errors on the host; without a device the library plans
+    for a 64 KB LDS limit, so the answers are fixed."""
+    binding, lib = _lib()
+    pol, lds = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    D = binding.qp_dims
+    assert lib.qp_plan(9, D(10, 20, 0), 0, ctypes.byref(pol), ctypes.byref(lds)) == binding.QP_EDTYPE
+    assert lib.qp_plan(binding.QP_F64, D(0, 20, 0), 0, ctypes.byref(pol), None) == binding.QP_EARG
+    assert lib.qp_plan(binding.QP_F64, D(10, 20, 0), 7, ctypes.byref(pol), None) == binding.QP_EARG
+    assert lib.qp_plan(binding.QP_F64, D(10, 20, 0), 0, None, None) == binding.QP_EARG
+    import torch
+    if torch.cuda.is_available():
+        return
+    # FP32 register tiles fit in 64 KB at nz = nineq = 100; FP64 ones do not (streamed tiles)
+    assert lib.qp_plan(binding.QP_F32, D(100, 100, 0), 0, ctypes.byref(pol), ctypes.byref(lds)) == 0
+    assert pol.value == binding.VARIANT_TILED and 0 < lds.value <= 64 * 1024
+    assert lib.qp_plan(binding.QP_F64, D(100, 100, 0), 0, ctypes.byref(pol), ctypes.byref(lds)) == 0
+    assert pol.value == binding.VARIANT_STREAM and 0 < lds.value <= 64 * 1024
+    assert lib.qp_plan(binding.QP_F64, D(100, 100, 0), binding.VARIANT_GENERIC, ctypes.byref(pol),
+                       ctypes.byref(lds)) == 0
+    assert pol.value == binding.VARIANT_GENERIC
