@@ -262,3 +262,23 @@ def test_unit_row_flag_falls_back_on_dense_g():
         d = _run(b, dtype)
         for k in ("z", "lam", "nu", "s", "iters", "dQ", "dG"):
             np.testing.assert_array_equal(a[k], d[k], err_msg=k)
+
+
+@pytest.mark.parametrize("n", [12, 90, 180])
+def test_unit_row_flag_with_equality_rows(n):
+    """The unit-row path with equality rows (Schur complement on A): QPs over the
+    probability simplex, z >= 0 written as G = -I, h = 0, and 1^T z = 1 (the
+    simplex layer of the paper's representational examples), against the oracle
+    replay; nz = 180 runs in FP32 only (the 16x16 register-tile grid)."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    base = synth.make_batch(seed=4040 + n, B=3, n=n, m=0, p=0)
+    G = np.broadcast_to(-np.eye(n), (3, n, n)).copy()
+    b = synth.QPBatch(base.Q, 2.0 * base.q, np.ones((3, 1, n)), np.ones((3, 1)), G, np.zeros((3, n)),
+                      base.g)
+    for dtype in ((np.float32,) if n > 128 else (np.float64, np.float32)):
+        tdt = torch.float64 if dtype == np.float64 else torch.float32
+        assert qb.plan(tdt, n, n, 1)[0] == qb.VARIANT_TILED
+        out = _run(b, dtype, opts_over={"flags": qb.FLAG_G_UNIT_ROWS})
+        _check(b, out, dtype, range(3))
+        assert np.allclose(out["z"].sum(axis=1), 1.0, atol=1e-5 if dtype == np.float64 else 1e-3)
