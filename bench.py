@@ -387,9 +387,9 @@ def main():
     if args.dtype is None:
         args.dtype = "f64"
     if args.gpus != 1:
-        print("bench.py measures one GPU only: every QP is independent and this build runs on a "
-              "single MI355X (see DESIGN.md for how the batch would shard); got --gpus %d"
-              % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: every QP is independent, so a batch shards across GPUs "
+              "by whole problems and each GPU runs this same path; got --gpus %d" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

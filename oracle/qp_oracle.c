@@ -18,7 +18,7 @@
  * unreduced matrix K exactly as printed under eq. cvxgen:affine (no block
  * elimination, no symmetrization), by dense LU with partial pivoting.
  *
- * Readings where the paper is silent (all stated in the design doc's readings list):
+ * Readings where the paper is silent:
  *   - sigma = (mu_aff / mu)^3 (Mehrotra's rule as used by CVXGEN);
  *   - one step length for primal and dual variables: alpha_aff = min(1, a_max)
  *     and alpha = min(1, 0.99 a_max), a_max the largest step keeping s, lambda
