@@ -107,21 +107,23 @@ struct BwdLayout {
 // iterations; it stops when a correction of d_z, or the next one predicted
 // from the rate of the last two, is below 1e-7 relative (about the resolution
 // of the FP32 result).
-// With `stage`, Q, G and A are copied to LDS once (the iteration reads them
-// four times per step); the choice depends on the problem's dims and the
-// device LDS size only, and the products run the same code on either copy.
+// stage >= 1: Q, G and A are copied to LDS once (the iteration reads them
+// four times per step); stage 2 also copies the stored factor (U, Wt, US),
+// which every projection reads twice.  The choice depends on the problem's
+// dims and the device LDS size only, and the same code runs on either copy.
 struct BwdMixedLayout {
-    int f, y, gz, r4, tp, tp2, gn, scr, qs, gs, as;     // FP32, offsets in floats
-    int x, r, gv, d, t1, t2, t3, tm, v, va, scr64, red; // FP64, offsets in doubles from dbase
-    int dbase, end;                                     // bytes
-    __host__ __device__ BwdMixedLayout(int n, int m, int p, bool stage) {
+    int f, y, gz, r4, tp, tp2, gn, scr, qs, gs, as, us, wts, uss; // FP32, offsets in floats
+    int x, r, gv, d, t1, t2, t3, tm, v, va, scr64, red;           // FP64, offsets in doubles from dbase
+    int dbase, end;                                               // bytes
+    __host__ __device__ BwdMixedLayout(int n, int m, int p, int stage) {
         const int N = pad4(n), M = pad4(m), Pp = pad4(p);
         int o = 0;
         f = o; o += N; y = o; o += N; gz = o; o += N;
         r4 = o; o += Pp; tp = o; o += Pp; tp2 = o; o += Pp; gn = o; o += Pp;
         scr = o; o += 512;
-        qs = gs = as = 0;
-        if (stage) { qs = o; o += n * n; gs = o; o += m * n; as = o; o += p * n; }
+        qs = gs = as = us = wts = uss = 0;
+        if (stage >= 1) { qs = o; o += n * n; gs = o; o += m * n; as = o; o += p * n; }
+        if (stage >= 2) { us = o; o += u_ld(n) * u_ld(n); wts = o; o += p * n; uss = o; o += p * p; }
         dbase = (o * 4 + 15) & ~15;
         int q = 0;
         x = q; q += N; r = q; q += N; gv = q; q += N; d = q; q += N;
@@ -131,8 +133,9 @@ struct BwdMixedLayout {
     }
 };
 
-__host__ __device__ inline bool bwd_mixed_stage(int n, int m, int p, int lds_limit) {
-    return BwdMixedLayout(n, m, p, true).end <= lds_limit;
+__host__ __device__ inline int bwd_mixed_stage(int n, int m, int p, int lds_limit) {
+    if (BwdMixedLayout(n, m, p, 2).end <= lds_limit) return 2;
+    return BwdMixedLayout(n, m, p, 1).end <= lds_limit ? 1 : 0;
 }
 
 size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit) {
@@ -140,7 +143,7 @@ size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit) {
                     : (size_t)BwdLayout(n, m, p).end * esz;
 }
 
-template <int NT, bool STAGE>
+template <int NT, int STAGE>
 __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int refine_steps) {
     const int n = P.n, m = P.m, p = P.p;
     const int tid = threadIdx.x;
@@ -153,14 +156,22 @@ __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int 
     const float *__restrict__ sl = P.s;
     float *fs = reinterpret_cast<float *>(smem);
     const float *Q = P.Q, *G = P.G, *A = P.A;
-    if constexpr (STAGE) {
+    if constexpr (STAGE >= 1) {
         float *qs = fs + Lo.qs, *gs = fs + Lo.gs, *as = fs + Lo.as;
         for (int e = tid; e < n * n; e += NT) qs[e] = P.Q[e];
         for (int e = tid; e < m * n; e += NT) gs[e] = P.G[e];
         for (int e = tid; e < p * n; e += NT) as[e] = P.A[e];
-        __syncthreads();
         Q = qs; G = gs; A = as;
     }
+    if constexpr (STAGE >= 2) {
+        float *us = fs + Lo.us, *wts = fs + Lo.wts, *uss = fs + Lo.uss;
+        const int lu = u_ld(n);
+        for (int e = tid; e < lu * lu; e += NT) us[e] = U[e];
+        for (int e = tid; e < p * n; e += NT) wts[e] = Wt[e];
+        for (int e = tid; e < p * p; e += NT) uss[e] = US[e];
+        U = us; Wt = wts; US = uss;
+    }
+    if constexpr (STAGE >= 1) __syncthreads();
     double *ds = reinterpret_cast<double *>(smem + Lo.dbase);
     float *f = fs + Lo.f, *y = fs + Lo.y, *gz = fs + Lo.gz, *r4 = fs + Lo.r4, *tp = fs + Lo.tp,
           *tp2 = fs + Lo.tp2, *gn = fs + Lo.gn, *scr = fs + Lo.scr;
@@ -266,10 +277,13 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         const BProb<T> P = bwd_problem<T>(L, j);
         if (!P.need) continue;
         if constexpr (sizeof(T) == 4) {
-            if (bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit))
-                bwd_solve_mixed<NT, true>(P, smem_raw, L.refine_steps);
+            const int stage = bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit);
+            if (stage == 2)
+                bwd_solve_mixed<NT, 2>(P, smem_raw, L.refine_steps);
+            else if (stage == 1)
+                bwd_solve_mixed<NT, 1>(P, smem_raw, L.refine_steps);
             else
-                bwd_solve_mixed<NT, false>(P, smem_raw, L.refine_steps);
+                bwd_solve_mixed<NT, 0>(P, smem_raw, L.refine_steps);
         } else {
         const int n = P.n, m = P.m, p = P.p;
         const BwdLayout Lo(n, m, p);
