@@ -138,9 +138,15 @@ __host__ __device__ inline int bwd_mixed_stage(int n, int m, int p, int lds_limi
     return BwdMixedLayout(n, m, p, 1).end <= lds_limit ? 1 : 0;
 }
 
+// FP64: G (read six times per refinement step) is copied to LDS after the
+// vectors when it fits; the choice depends on dims and the device LDS only.
+__host__ __device__ inline bool bwd_stage_g64(int n, int m, int p, int lds_limit) {
+    return ((size_t)BwdLayout(n, m, p).end + (size_t)m * n) * 8 <= (size_t)lds_limit;
+}
+
 size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit) {
-    return esz == 4 ? (size_t)BwdMixedLayout(n, m, p, bwd_mixed_stage(n, m, p, lds_limit)).end
-                    : (size_t)BwdLayout(n, m, p).end * esz;
+    if (esz == 4) return (size_t)BwdMixedLayout(n, m, p, bwd_mixed_stage(n, m, p, lds_limit)).end;
+    return ((size_t)BwdLayout(n, m, p).end + (bwd_stage_g64(n, m, p, lds_limit) ? (size_t)m * n : 0)) * esz;
 }
 
 template <int NT, int STAGE>
@@ -293,7 +299,12 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         const T *Wt = (const T *)(P.state + SL.off_Wt);
         const T *US = (const T *)(P.state + SL.off_US);
         const T *__restrict__ Q = P.Q;
-        const T *__restrict__ G = P.G;
+        const bool sg = bwd_stage_g64(n, m, p, L.lds_limit);
+        if (sg) {
+            T *gs = sm + Lo.end;
+            for (int e = tid; e < m * n; e += NT) gs[e] = P.G[e];
+        }
+        const T *__restrict__ G = sg ? sm + Lo.end : P.G;
         const T *__restrict__ A = P.A;
         T *z = sm + Lo.z, *g = sm + Lo.g, *dz = sm + Lo.dz, *f = sm + Lo.f, *y = sm + Lo.y,
           *tn = sm + Lo.tn, *tn2 = sm + Lo.tn2, *r1 = sm + Lo.r1, *ez = sm + Lo.ez;
