@@ -81,13 +81,19 @@ def dedicated_stream(device_index: int, k: int):
     them), so they are reused across servers."""
     import ctypes
     import os
+    import warnings
     import torch
     with _DEDICATED_LOCK:
         pool = _DEDICATED.setdefault(device_index, [])
         while len(pool) <= k:
             with torch.cuda.device(device_index):
                 torch.cuda.init()
-                hip = ctypes.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | ctypes.RTLD_GLOBAL)
+                hip = _loaded_hip_runtime(ctypes, os)
+                if hip is None:  # only the queue assignment is lost, not correctness
+                    warnings.warn("HIP runtime not found among loaded libraries; serving slots use "
+                                  "ordinary streams, which may share hardware queues")
+                    pool.append(torch.cuda.Stream(device=torch.device("cuda", device_index)))
+                    continue
                 cus = torch.cuda.get_device_properties(device_index).multi_processor_count
                 words = (cus + 31) // 32
                 mask = (ctypes.c_uint32 * words)(*([0xFFFFFFFF] * words))
@@ -97,6 +103,16 @@ def dedicated_stream(device_index: int, k: int):
                     raise RuntimeError("hipExtStreamCreateWithCUMask failed: %d" % rc)
                 pool.append(torch.cuda.ExternalStream(s.value, device=torch.device("cuda", device_index)))
         return pool[k]
+
+
+def _loaded_hip_runtime(ctypes, os):
+    """The HIP runtime torch already loaded (never a second copy: RTLD_NOLOAD)."""
+    for name in ("libamdhip64.so.7", "libamdhip64.so.6", "libamdhip64.so"):
+        try:
+            return ctypes.CDLL(name, mode=os.RTLD_NOLOAD | ctypes.RTLD_GLOBAL)
+        except OSError:
+            continue
+    return None
 
 
 class DeviceBackend:
