@@ -47,3 +47,31 @@ def test_served_results_equal_alone_results():
         if i % 10 == 0:
             ref = oracle_replay(P, res[i]["iters"], np.float32)
             assert z_err(res[i]["z"], ref["z"]) <= TOL_Z[np.float32]
+
+
+def test_served_fp64_results_equal_alone_results():
+    """The same in FP64: 30 requests (nz up to 128), results bitwise equal to the
+    request solved alone, and z against the oracle for every fifth."""
+    import torch
+    from paper_1703_00443_amd.serve import Server
+    from paper_1703_00443_amd.varlen import VarlenBatch
+    dims = synth.serving_dims(56, 30, n_lo=8, n_hi=128)
+    probs = synth.make_varlen(56, [d[:3] for d in dims])
+    srv = Server(dtype=torch.float64, hbm_budget=1 << 30)
+    futs = [srv.submit(P, need_backward=d[3], dl_dz=P["g"] if d[3] else None) for P, d in zip(probs, dims)]
+    res = [f.result(timeout=120) for f in futs]
+    srv.close()
+    assert srv.stats["admitted"] == len(probs)
+    for i, P in enumerate(probs):
+        one = VarlenBatch([P], dtype=torch.float64, table=srv.backend.table)
+        one.forward()
+        if dims[i][3]:
+            one.backward(one.pack_vectors([P["g"]]))
+        torch.cuda.synchronize()
+        a = one.result(0)
+        np.testing.assert_array_equal(res[i]["z"], a["z"])
+        if dims[i][3]:
+            np.testing.assert_array_equal(res[i]["dQ"], a["dQ"])
+        if i % 5 == 0:
+            ref = oracle_replay(P, res[i]["iters"], np.float64)
+            assert z_err(res[i]["z"], ref["z"]) <= TOL_Z[np.float64]

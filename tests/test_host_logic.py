@@ -85,3 +85,20 @@ def test_algorithmic_flops_counts():
     # backward bytes: read Q, G, z, lam, s, dl/dz and the factor (U, D); write
     # dQ, dq, dG, dh  ->  3 n^2 + 2 m n + 3 n + 4 m elements = 50700 at this shape
     assert bench.backward_bytes(n, m, 0, 8) == 8 * 50700
+
+
+def test_box_batch_structure():
+    """Box QPs: G = [I; -I] (rows are signed unit vectors), h = [u; -l] with
+    l < 0 < u (z = 0 is strictly feasible), Q symmetric positive definite,
+    and each problem regenerates alone."""
+    b = synth.box_batch(seed=3, B=4, n=7)
+    n, m, p = b.dims
+    assert (n, m, p) == (7, 14, 0)
+    for i in range(4):
+        G = b.G[i]
+        assert np.all((G != 0).sum(axis=1) == 1) and np.all(np.abs(G[G != 0]) == 1)
+        assert np.array_equal(G[:n], np.eye(n)) and np.array_equal(G[n:], -np.eye(n))
+        assert np.all(b.h[i] > 0)
+        assert np.allclose(b.Q[i], b.Q[i].T) and np.linalg.eigvalsh(b.Q[i]).min() > 0
+    one = synth.box_batch(seed=3, B=2, n=7)
+    assert np.array_equal(one.Q[1], b.Q[1]) and np.array_equal(one.h[1], b.h[1])
