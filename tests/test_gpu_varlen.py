@@ -170,3 +170,24 @@ def test_uneven_4096_stratified_256_vs_oracle():
         for i, ez, eg in ex.map(check, sample):
             assert ez <= TOL_Z[np.float32], (i, dims[i], ez)
             assert eg <= TOL_G[np.float32], (i, dims[i], eg)
+
+
+def test_unit_row_flag_is_accepted_and_dense_in_uneven_batches():
+    """qp_forward_varlen accepts QP_FLAG_G_UNIT_ROWS and runs the dense path for
+    every problem: bitwise the unflagged result (box QPs of two sizes)."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd.varlen import VarlenBatch
+    probs = []
+    for n in (20, 70):
+        b = synth.box_batch(seed=n, B=2, n=n)
+        for i in range(2):
+            P = b.problem(i)
+            P["A"], P["b"] = None, None
+            probs.append(P)
+    a = VarlenBatch(probs, dtype=torch.float32)
+    d = VarlenBatch(probs, dtype=torch.float32)
+    a.forward(qb.default_opts(torch.float32, flags=qb.FLAG_G_UNIT_ROWS))
+    d.forward()
+    torch.cuda.synchronize()
+    assert torch.equal(a.z, d.z) and torch.equal(a.lam, d.lam) and torch.equal(a.iters, d.iters)
