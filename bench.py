@@ -111,6 +111,19 @@ def cpu_baseline(batch_np, target_cpu_s=12.0):
                       "one QP per thread" % (count, min(count, B) - 1)}
 
 
+def calib_copy(mb, dev):
+    """Three device copies of `mb` MiB: the reference kernel that scales the HBM
+    counters of a rocprofv3 --pmc run.  Returns the bytes copied per copy."""
+    import torch
+    nel = mb * (1 << 20) // 4
+    src = torch.ones(nel, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return nel * 4
+
+
 def bench_uneven(args):
     """4096 QPs (default), nz ~ U{8..256}, nineq = 2 nz, neq ~ U{0..nz/4}, FP32, one
     persistent launch per pass (forward + backward), HIP-graph captured."""
@@ -146,10 +159,12 @@ def bench_uneven(args):
     torch.cuda.synchronize()
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     fwd_tf = flops / (fwd_ms * 1e-3) / 1e12
+    if args.calib_copy_mb:
+        calib_copy(args.calib_copy_mb, torch.device("cuda:0"))
     # per size bucket: the bucket's problems alone, one launch each (forward + backward)
     buckets = []
     edges = (8, 32, 64, 128, 192, 256)
-    for lo, hi in zip(edges[:-1], edges[1:]):
+    for lo, hi in zip(edges[:-1], edges[1:]) if not args.no_buckets else ():
         idx = [i for i, d in enumerate(dims) if (lo < d[0] <= hi) or (lo == 8 and d[0] == 8)]
         if not idx:
             continue
@@ -379,6 +394,8 @@ def main():
                          "one persistent launch; serving: Poisson request stream, p50/p99 latency; "
                          "sweep: the paper's size and batch-size timing experiments")
     ap.add_argument("--count", type=int, default=0, help="problems/requests for uneven/serving")
+    ap.add_argument("--no-buckets", action="store_true",
+                    help="uneven: skip the per-bucket launches (counter runs of the full launch)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, run 3 device copies of this many MiB "
                          "(reference kernel for HBM counter calibration under rocprofv3)")
@@ -472,13 +489,7 @@ def main():
     }
 
     if args.calib_copy_mb:
-        nel = args.calib_copy_mb * (1 << 20) // 4
-        src = torch.ones(nel, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = nel * 4
+        out["calib_copy_bytes"] = calib_copy(args.calib_copy_mb, dev)
 
     if not args.no_plain:
         # the same library called once per QP with a host sync per call
