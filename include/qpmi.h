@@ -57,9 +57,10 @@ enum {
     QP_STATUS_OPTIMAL = 0,   /* stopping test met (see qp_opts.tol)                     */
     QP_STATUS_MAX_ITER = 1,  /* max_iter Newton steps taken; last iterate returned      */
     QP_STATUS_BREAKDOWN = 2, /* non-positive or non-finite pivot in the factorization of
-                                the returned iterate; the iterate is returned, the
-                                stored factor (and so any backward) is undefined         */
-    QP_STATUS_NONFINITE = 3, /* non-finite input or iterate                              */
+                                the initial point or the first iterate; no factor is
+                                stored and the backward writes zero gradients            */
+    QP_STATUS_NONFINITE = 3, /* non-finite input or iterate; no factor is stored and the
+                                backward writes zero gradients                           */
     QP_STATUS_STALLED = 4    /* the factorization of the next iterate lost positive
                                 definiteness in working precision before the tolerance was
                                 met; the last iterate whose factorization succeeded is
@@ -167,7 +168,9 @@ int32_t qp_forward_batched(qp_dtype dtype, int32_t batch, qp_dims dims, const qp
  *   dQ [batch*nz*nz], dq [batch*nz], dA [batch*neq*nz], db [batch*neq],
  *   dG [batch*nineq*nz], dh [batch*nineq].
  * Gradients of batch-shared inputs (stride 0) are still written per problem;
- * summing them over the batch is the caller's choice. */
+ * summing them over the batch is the caller's choice.  A problem whose forward
+ * ended BREAKDOWN or NONFINITE has no stored factor: its gradients are written
+ * as zeros. */
 int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims dims, const qp_data *data,
                             const qp_opts *opts, const void *z, const void *lam, const void *nu,
                             const void *s, const void *state, const void *dl_dz, void *dQ,
@@ -207,10 +210,14 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
 
 /* Backward of an uneven batch.  Gradient outputs use the input offsets of the
  * descriptors (dQ at desc.Q, dq at desc.q, ... in packed buffers shaped like the
- * inputs); `grad_base` may be NULL for problems that need no gradient only if
- * `need_dev` marks them: need_dev (device, `count` int32, NULL = all) selects
- * the problems whose gradients are computed; others are skipped. dl_dz uses
- * the z offsets. */
+ * inputs); need_dev (device, `count` int32, NULL = all) selects the problems
+ * whose gradients are computed; others are skipped (their gradient entries are
+ * left untouched). dl_dz uses the z offsets.  ws holds the adjoint vectors of
+ * problem i at element offset desc.z + desc.lam + desc.nu (nz + nineq + neq
+ * entries): with z, lam, nu offsets packed in descriptor order these are the
+ * prefix sums of nz + nineq + neq; overlapping adjoint ranges are rejected
+ * (QP_EARG).  Problems whose forward ended BREAKDOWN or NONFINITE get zero
+ * gradients. */
 int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *desc_dev,
                            const qp_problem_desc *desc_host, const int32_t *need_dev,
                            const void *base_in, const qp_opts *opts, const void *z,

@@ -3,6 +3,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "qp_internal.h"
 
@@ -217,11 +219,13 @@ int32_t qp_varlen_workspace_query(qp_dtype dtype, int32_t count, const qp_proble
     const int esz = esize(dtype);
     for (int i = 0; i < count; ++i) {
         if (!desc_ok(dh[i])) return QP_EARG;
-        b = std::max(b, adj_stride_elems(dh[i].nz, dh[i].nineq, dh[i].neq));
+        // adjoint vectors packed at desc.z + desc.lam + desc.nu: the extent of the
+        // packed z, lam, nu offsets bounds them
+        b = std::max(b, (size_t)(dh[i].z + dh[i].lam + dh[i].nu) + dh[i].nz + dh[i].nineq + dh[i].neq);
         st += state_layout(esz, dh[i].nz, dh[i].nineq, dh[i].neq).bytes;
     }
     if (fwd) *fwd = kAlignBytes;  // work-queue counter
-    if (bwd) *bwd = (size_t)count * b * esz;
+    if (bwd) *bwd = b * esz;
     if (state_total) *state_total = st;
     return QP_OK;
 }
@@ -290,16 +294,20 @@ int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc 
     if (ws_bytes < need || !ws) return QP_EWS;
     const int esz = esize(dtype);
     int lds = 0, rows = 0;
-    size_t stride = 0;
     const int lim = device_lds_limit();
+    std::vector<std::pair<int64_t, int64_t>> adj(count);
     for (int i = 0; i < count; ++i) {
         const qp_problem_desc &d = desc_host[i];
         const size_t b = bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim);
         if (b > (size_t)lim) return QP_ETOOBIG;
         lds = std::max(lds, (int)b);
         rows = std::max(rows, d.nz + d.nineq + d.neq + 1);
-        stride = std::max(stride, adj_stride_elems(d.nz, d.nineq, d.neq));
+        adj[i] = {d.z + d.lam + d.nu, (int64_t)d.nz + d.nineq + d.neq};
     }
+    // the adjoint vectors of two problems must not overlap (packed offsets do not)
+    std::sort(adj.begin(), adj.end());
+    for (int i = 1; i < count; ++i)
+        if (adj[i - 1].first + adj[i - 1].second > adj[i].first) return QP_EARG;
     BwdLaunch L;
     memset(&L, 0, sizeof(L));
     L.count = count;
@@ -311,7 +319,7 @@ int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc 
     L.dl_dz = dl_dz;
     L.grad_base = grad_base;
     L.adj = ws;
-    L.adj_stride = stride;
+    L.adj_stride = 0;  // varlen: problem j's adjoint at desc.z + desc.lam + desc.nu
     L.refine_steps = opts->refine_steps;
     L.lds_bytes = lds;
     L.lds_limit = lim;

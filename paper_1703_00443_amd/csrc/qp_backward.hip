@@ -24,6 +24,7 @@ struct BProb {
     const T *g;
     T *adj;
     bool need;
+    bool valid;  // the forward stored a factor (else the gradients are zero)
     // gradient outputs (nullable)
     T *dQ, *dq, *dA, *db, *dG, *dh;
 };
@@ -31,8 +32,8 @@ struct BProb {
 template <typename T>
 __device__ __forceinline__ BProb<T> bwd_problem(const BwdLaunch &L, int j) {
     BProb<T> P;
-    P.adj = (T *)L.adj + (size_t)j * L.adj_stride;
     if (L.desc == nullptr) {
+        P.adj = (T *)L.adj + (size_t)j * L.adj_stride;
         P.n = L.nz; P.m = L.nineq; P.p = L.neq;
         P.Q = (const T *)L.Q + (size_t)j * L.sQ;
         P.A = (const T *)L.A + (size_t)j * L.sA;
@@ -54,6 +55,7 @@ __device__ __forceinline__ BProb<T> bwd_problem(const BwdLaunch &L, int j) {
     } else {
         const qp_problem_desc d = L.desc[j];
         const T *base = (const T *)L.base_in;
+        P.adj = (T *)L.adj + d.z + d.lam + d.nu;  // packed: prefix sum of nz + nineq + neq
         P.n = d.nz; P.m = d.nineq; P.p = d.neq;
         P.Q = base + d.Q; P.A = base + d.A; P.G = base + d.G;
         P.z = (const T *)L.z + d.z; P.lam = (const T *)L.lam + d.lam;
@@ -65,6 +67,7 @@ __device__ __forceinline__ BProb<T> bwd_problem(const BwdLaunch &L, int j) {
         P.dQ = gb + d.Q; P.dq = gb + d.q; P.dA = gb + d.A;
         P.db = gb + d.b; P.dG = gb + d.G; P.dh = gb + d.h;
     }
+    P.valid = *reinterpret_cast<const int32_t *>(P.state + state_layout(sizeof(T), P.n, P.m, P.p).off_valid) != 0;
     return P;
 }
 
@@ -282,6 +285,10 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
     for (int j = blockIdx.x; j < L.count; j += gridDim.x) {
         const BProb<T> P = bwd_problem<T>(L, j);
         if (!P.need) continue;
+        if (!P.valid) {  // no factor was stored: zero adjoint (the gradients are written as zeros)
+            for (int e = tid; e < P.n + P.m + P.p; e += NT) P.adj[e] = T(0);
+            continue;
+        }
         if constexpr (sizeof(T) == 4) {
             const int stage = bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit);
             if (stage == 2)
@@ -385,7 +392,11 @@ __global__ __launch_bounds__(NT) void qp_grad_assemble_kernel(BwdLaunch L) {
     const int R = n + m + p + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const T *dz = P.adj, *dl = P.adj + n, *dn = P.adj + n + m;
-    const T *z = P.z;
+    // without a stored factor (forward BREAKDOWN / NONFINITE) every gradient is
+    // zero: the adjoint is zero and the iterate is not read (it may be non-finite)
+    const T *z = P.valid ? P.z : P.adj;  // the adjoint's zeros stand in for z
+    const T *lamv = P.valid ? P.lam : P.adj + n;
+    const T *nuv = P.valid ? P.nu : P.adj + n + m;
     for (int rr = w; rr < kRowsPerBlock; rr += NW) {
         const int r = blockIdx.y * kRowsPerBlock + rr;
         if (r >= R) break;
@@ -397,13 +408,13 @@ __global__ __launch_bounds__(NT) void qp_grad_assemble_kernel(BwdLaunch L) {
         } else if (r < n + m) {
             if (!P.dG) continue;
             const int k = r - n;
-            const T a = dl[k], lk = P.lam[k];
+            const T a = dl[k], lk = lamv[k];
             T *row = P.dG + (size_t)k * n;
             for (int c = lane; c < n; c += 64) row[c] = a * z[c] + lk * dz[c];
         } else if (r < n + m + p) {
             if (!P.dA) continue;
             const int k = r - n - m;
-            const T a = dn[k], nk = P.nu[k];
+            const T a = dn[k], nk = nuv[k];
             T *row = P.dA + (size_t)k * n;
             for (int c = lane; c < n; c += 64) row[c] = a * z[c] + nk * dz[c];
         } else {

@@ -115,6 +115,23 @@ __device__ __forceinline__ void block_reduce3(T &vsum, T &vmax, T &vmin, T *red)
     vsum = a; vmax = b; vmin = c;
 }
 
+// Four values at once: a sum, two maxima and a minimum (red: 4 * NT/64 slots).
+template <typename T, int NT>
+__device__ __forceinline__ void block_reduce4(T &vsum, T &vmax, T &vmax2, T &vmin, T *red) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T a = wave_sum(vsum), b = wave_max(vmax), c = wave_max(vmax2), d = wave_min(vmin);
+    if (lane == 0) { red[w] = a; red[NW + w] = b; red[2 * NW + w] = c; red[3 * NW + w] = d; }
+    __syncthreads();
+    a = red[0]; b = red[NW]; c = red[2 * NW]; d = red[3 * NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+        a += red[i]; b = fmax(b, red[NW + i]); c = fmax(c, red[2 * NW + i]); d = fmin(d, red[3 * NW + i]);
+    }
+    __syncthreads();
+    vsum = a; vmax = b; vmax2 = c; vmin = d;
+}
+
 template <typename T, int NT>
 __device__ __forceinline__ T block_sum(T v, T *red) {
     T mx = 0, mn = 0;

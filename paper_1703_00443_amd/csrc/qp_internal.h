@@ -19,22 +19,29 @@ __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a -
 __host__ __device__ constexpr int u_ld(int n) { return (n + 15) & ~15; }
 
 // Per-problem factor state, in elements of T, each region 256-byte aligned:
+//   valid [1 int32]  1 when the forward stored the factor of the returned
+//                    iterate (status OPTIMAL, MAX_ITER or STALLED), 0 when it
+//                    did not (BREAKDOWN, NONFINITE); the backward then writes
+//                    zero gradients for the problem
 //   U   [ldu*ldu]    ldu = u_ld(nz); upper triangle (incl. diagonal) of the
 //                    leading nz x nz block = L^{-T}, L L^T = Qs + G^T D G
 //   D   [nineq]      lambda / s at the returned iterate
 //   Wt  [neq*nz]     Wt = (L^{-1} A^T)^T
 //   US  [neq*neq]    upper triangle = LS^{-T}, LS LS^T = Wt Wt^T (Schur complement)
+//   gw  [nineq]      forward scratch: the 1-norms of the rows of G
 struct StateLayout {
-    size_t off_U, off_D, off_Wt, off_US, bytes;
+    size_t off_valid, off_U, off_D, off_Wt, off_US, off_gw, bytes;
 };
 
 __host__ __device__ inline StateLayout state_layout(int esz, int n, int m, int p) {
     StateLayout s;
     size_t o = 0;
+    s.off_valid = o; o += kAlignBytes;
     s.off_U = o; o += align_up((size_t)u_ld(n) * u_ld(n) * esz, kAlignBytes);
     s.off_D = o; o += align_up((size_t)(m > 0 ? m : 1) * esz, kAlignBytes);
     s.off_Wt = o; o += align_up((size_t)(p > 0 ? p * n : 1) * esz, kAlignBytes);
     s.off_US = o; o += align_up((size_t)(p > 0 ? p * p : 1) * esz, kAlignBytes);
+    s.off_gw = o; o += align_up((size_t)(m > 0 ? m : 1) * esz, kAlignBytes);
     s.bytes = o;
     return s;
 }
@@ -79,8 +86,9 @@ struct BwdLaunch {
     void *dQ, *dq, *dA, *db, *dG, *dh;
     // varlen-mode gradient base (inputs' offsets)
     void *grad_base;
-    void *adj;                // [count * adj_stride] adjoint vectors (d_z, d_lam~, d_nu)
-    size_t adj_stride;        // elements per problem
+    void *adj;                // adjoint vectors (d_z, d_lam~, d_nu) of every problem
+    size_t adj_stride;        // uniform mode: elements per problem (varlen mode: problem j at
+                              // desc.z + desc.lam + desc.nu, the prefix sum of nz + nineq + neq)
     int refine_steps;
     int lds_bytes;
     int lds_limit;            // device LDS per workgroup (per-problem plans depend on it only)

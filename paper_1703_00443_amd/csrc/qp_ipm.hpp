@@ -103,8 +103,8 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
                           int32_t *status, int32_t *iters) {
     const int n = P.n, m = P.m, p = P.p;
     const int tid = threadIdx.x;
-    T *z = sm + Lo.z, *rx = sm + Lo.rx, *f = sm + Lo.f, *dza = sm + Lo.dza, *dzc = sm + Lo.dzc,
-      *tn = sm + Lo.tn, *tn2 = sm + Lo.tn2;
+    T *z = sm + Lo.z, *rx = sm + Lo.rx, *f = sm + Lo.f, *y = sm + Lo.y, *dza = sm + Lo.dza,
+      *dzc = sm + Lo.dzc, *tn = sm + Lo.tn, *tn2 = sm + Lo.tn2;
     T *s = sm + Lo.s, *lam = sm + Lo.lam, *rz = sm + Lo.rz, *D = sm + Lo.D, *dsa = sm + Lo.dsa,
       *dla = sm + Lo.dla, *w = sm + Lo.w, *tm = sm + Lo.tm;
     T *dsc = tm, *dlc = w;  // combined step, written over the entries just read
@@ -137,6 +137,9 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     }
     int st = QP_STATUS_MAX_ITER, it = 0;
     bool stalled = false;  // re-running the previous iterate after a breakdown
+    constexpr T kEps = sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
+    T *gw = reinterpret_cast<T *>(P.state + state_layout(sizeof(T), n, m, p).off_gw);
+    T gcol = 0;
     if (!fin) {
         st = QP_STATUS_NONFINITE;
         for (int e = tid; e < n; e += NT) z[e] = 0;
@@ -146,6 +149,24 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         goto finish;
     }
     fac.prepare();
+
+    // Row 1-norms of G (state scratch) and the largest column 1-norm: they bound
+    // how much the rounding of G dz, multiplied by D = lambda / s when the
+    // multiplier step is recovered, can leave in the first Newton row (below).
+    {
+        for (int k = tid; k < m; k += NT) {
+            T a = 0;
+            for (int j = 0; j < n; ++j) a += fabs(PG[(size_t)k * n + j]);
+            gw[k] = a;
+        }
+        for (int j = tid; j < n; j += NT) {
+            T a = 0;
+            for (int k = 0; k < m; ++k) a += fabs(PG[(size_t)k * n + j]);
+            gcol = fmax(gcol, a);
+        }
+        T d0 = 0, d1 = pinf<T>();
+        block_reduce3<T, NT>(d0, gcol, d1, red);  // its barriers also publish gw
+    }
 
     // ---- initial point: K with the (D(lambda), D(s)) pair replaced by (I, I)
     for (int e = tid; e < m; e += NT) D[e] = T(1);
@@ -288,7 +309,9 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         __syncthreads();
         fac.solve(f, tp, dzc, dnc);
         fac.g_mv(dzc, tm);
-        amin = pinf<T>(); d0 = 0; d1 = 0;
+        // combined direction (dz in dza, dnu in dna, ds in tm, dlam in w)
+        amin = pinf<T>(); d0 = 0;
+        T emax = 0, dzmax = 0;
         for (int k = tid; k < m; k += NT) {
             const T dsc_k = -tm[k];
             const T dlc_k = w[k] - D[k] * dsc_k;
@@ -298,12 +321,72 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             dlc[k] = dl;
             if (ds < T(0)) amin = fmin(amin, -s[k] / ds);
             if (dl < T(0)) amin = fmin(amin, -lam[k] / dl);
+            emax = fmax(emax, D[k] * gw[k]);
         }
-        block_reduce3<T, NT>(d0, d1, amin, red);
+        for (int i = tid; i < n; i += NT) {
+            const T dz = dza[i] + dzc[i];
+            dza[i] = dz;
+            dzmax = fmax(dzmax, fabs(dz));
+        }
+        for (int k = tid; k < p; k += NT) dna[k] += dnc[k];
+        block_reduce4<T, NT>(d0, emax, dzmax, amin, red);
+
+        // One step of iterative refinement of the combined direction on the
+        // residual of the unreduced Newton system, with the same factor, when
+        // the bound eps |dz| max_k(D_k |G_k|_1) max_j |G^T e_j|_1 on the error
+        // that recovering dlam = c + D G dz leaves in the first row reaches a
+        // quarter of the tolerance (large D near the end of the solve).  Without
+        // it the dual residual can grow from one iterate to the next there
+        // instead of shrinking with the step.
+        if (kEps * dzmax * emax * gcol >= T(0.25) * tol) {
+            // e2 = (sigma mu - s lam - dsa dla) - (lam ds + s dl)        -> dla
+            for (int k = tid; k < m; k += NT)
+                dla[k] = (sigma * mu - s[k] * lam[k] - dsa[k] * dla[k]) - (lam[k] * dsc[k] + s[k] * dlc[k]);
+            __syncthreads();
+            fac.g_mv(dza, dsa);    // G dz
+            fac.qs_mv(dza, tn);    // Qs dz
+            fac.gt_mv(dlc, tn2);   // G^T dlam
+            if (p > 0) {
+                mv_cols<T, NT>(A, n, p, n, dna, y);  // A^T dnu
+                mv_rows<T, NT>(A, n, p, n, dza, tp);  // A dz
+                __syncthreads();
+            }
+            // e3 = rz - (G dz + ds) -> dsa;  c = (e2 - lam e3) / s -> dla
+            for (int k = tid; k < m; k += NT) {
+                const T e3 = rz[k] - (dsa[k] + dsc[k]);
+                dsa[k] = e3;
+                dla[k] = (dla[k] - lam[k] * e3) / s[k];
+            }
+            // e1 = rx - (Qs dz + G^T dlam + A^T dnu) -> f;  e4 = ry - A dz -> tp2
+            for (int i = tid; i < n; i += NT) {
+                T acc = tn[i] + tn2[i];
+                if (p > 0) acc += y[i];
+                f[i] = rx[i] - acc;
+            }
+            for (int k = tid; k < p; k += NT) tp2[k] = ry[k] - tp[k];
+            __syncthreads();
+            fac.gt_mv(dla, tn);    // G^T c
+            for (int i = tid; i < n; i += NT) f[i] -= tn[i];
+            __syncthreads();
+            fac.solve(f, tp2, dzc, dnc);
+            fac.g_mv(dzc, rz);     // G ddz (r_s is not read again in this step)
+            amin = pinf<T>(); d0 = 0; d1 = 0;
+            for (int k = tid; k < m; k += NT) {
+                const T ds = dsc[k] + (dsa[k] - rz[k]);          // + e3 - G ddz
+                const T dl = dlc[k] + (dla[k] + D[k] * rz[k]);   // + c + D G ddz
+                dsc[k] = ds;
+                dlc[k] = dl;
+                if (ds < T(0)) amin = fmin(amin, -s[k] / ds);
+                if (dl < T(0)) amin = fmin(amin, -lam[k] / dl);
+            }
+            for (int i = tid; i < n; i += NT) dza[i] += dzc[i];
+            for (int k = tid; k < p; k += NT) dna[k] += dnc[k];
+            block_reduce3<T, NT>(d0, d1, amin, red);
+        }
         const T alpha = fmin(T(1), T(0.99) * amin);
-        for (int i = tid; i < n; i += NT) z[i] += alpha * (dza[i] + dzc[i]);
+        for (int i = tid; i < n; i += NT) z[i] += alpha * dza[i];
         for (int k = tid; k < m; k += NT) { s[k] += alpha * dsc[k]; lam[k] += alpha * dlc[k]; }
-        for (int k = tid; k < p; k += NT) nu[k] += alpha * (dna[k] + dnc[k]);
+        for (int k = tid; k < p; k += NT) nu[k] += alpha * dna[k];
         __syncthreads();
     }
 
@@ -314,7 +397,14 @@ finish:
     for (int i = tid; i < n; i += NT) Pz[i] = z[i];
     for (int k = tid; k < m; k += NT) { Ps[k] = s[k]; Plam[k] = lam[k]; }
     for (int k = tid; k < p; k += NT) Pnu[k] = nu[k];
-    if (tid == 0) { status[Pout] = st; iters[Pout] = it; }
+    if (tid == 0) {
+        status[Pout] = st;
+        iters[Pout] = it;
+        // the factor of the returned iterate is in the state unless the solve
+        // broke down or met a non-finite value (the backward then writes zeros)
+        *reinterpret_cast<int32_t *>(P.state + state_layout(sizeof(T), n, m, p).off_valid) =
+            (st == QP_STATUS_BREAKDOWN || st == QP_STATUS_NONFINITE) ? 0 : 1;
+    }
     __syncthreads();
 }
 

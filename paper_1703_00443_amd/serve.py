@@ -53,18 +53,52 @@ class Request:
     future: Future = field(default_factory=Future)
     dims: tuple = ()
     cls: int = 0
+    fwd_bytes: int = 0
+    bwd_bytes: int = 0
+
+
+def state_bytes_host(esz: int, n: int, m: int, p: int) -> int:
+    """qp_state_bytes without the library: the validity word, then U (leading
+    dimension nz rounded up to 16), D, Wt, US and the row norms of G, each
+    region 256-byte aligned.
+    A CPU test checks it against the library's answer."""
+    al = lambda v: (v + 255) // 256 * 256
+    ld = (n + 15) & ~15
+    return int(256 + al(ld * ld * esz) + al(max(m, 1) * esz) + al((p * n if p else 1) * esz)
+               + al((p * p if p else 1) * esz) + al(max(m, 1) * esz))
+
+
+def footprint_parts(n: int, m: int, p: int, esz: int):
+    """(forward bytes, backward bytes) a request occupies in an uneven-batch
+    launch: the forward part is its packed inputs, outputs (z, lam, s, nu), factor
+    state, status and iters; the backward part is its share of the gradient buffer
+    (shaped like the inputs) and of the packed adjoint workspace.  A launch
+    allocates the backward part of EVERY request it holds as soon as one of them
+    asks for a backward (the gradient buffer covers all inputs)."""
+    inputs = n * n + n + p * n + p + m * n + m
+    # + status, iters (8 bytes), descriptor (96) and launch-order entry (4)
+    fwd = esz * (inputs + n + 2 * m + p) + state_bytes_host(esz, n, m, p) + 108
+    bwd = esz * (inputs + n + m + p)
+    return int(fwd), int(bwd)
+
+
+# launch-wide device bytes beyond the requests' own: the work-queue counter and the
+# caching allocator's rounding of each of a launch's tensors (512 bytes apiece)
+LAUNCH_OVERHEAD = 16384
 
 
 def footprint_bytes(n: int, m: int, p: int, esz: int, need_backward: bool) -> int:
-    """Device bytes one request occupies while in flight: packed inputs, outputs,
-    factor state, and for a backward the gradients and adjoint workspace."""
-    inputs = n * n + n + p * n + p + m * n + m
-    outputs = n + 2 * m + p
-    state = n * n + m + p * n + p * p + 4 * 64
-    total = inputs + outputs + state
-    if need_backward:
-        total += inputs + n + (n + m + p + 64)
-    return int(total * esz + 4096)
+    """Device bytes one request occupies when it is launched alone."""
+    f, b = footprint_parts(n, m, p, esz)
+    return f + (b if need_backward else 0) + LAUNCH_OVERHEAD
+
+
+def batch_bytes(reqs) -> int:
+    """Device bytes of one launch of these requests (see footprint_parts)."""
+    total = LAUNCH_OVERHEAD + sum(r.fwd_bytes for r in reqs)
+    if any(r.need_backward for r in reqs):
+        total += sum(r.bwd_bytes for r in reqs)
+    return total
 
 
 _DEDICATED: Dict[int, list] = {}
@@ -217,10 +251,11 @@ class Server:
         n = Q.shape[0]
         m = 0 if problem.get("G") is None else int(np.asarray(problem["G"]).reshape(-1, n).shape[0])
         p = 0 if problem.get("A") is None else int(np.asarray(problem["A"]).reshape(-1, n).shape[0])
-        fp = footprint_bytes(n, m, p, self.esz, need_backward)
+        fb, bb = footprint_parts(n, m, p, self.esz)
+        fp = fb + (bb if need_backward else 0) + LAUNCH_OVERHEAD
         req = Request(problem, need_backward, None if dl_dz is None else np.asarray(dl_dz), fp,
                       time.perf_counter(), dims=(n, m, p),
-                      cls=bisect.bisect_left(self.class_bounds, n))
+                      cls=bisect.bisect_left(self.class_bounds, n), fwd_bytes=fb, bwd_bytes=bb)
         if self.failed is not None:
             req.future.set_exception(RuntimeError("server stopped after an error: %r" % (self.failed,)))
             return req.future
@@ -285,14 +320,23 @@ class Server:
             if cls is None:
                 break
             batch, nbytes = [], 0
+            sum_f = sum_b = 0
+            any_b = False
             kept = collections.deque()
             for r in self.waiting:
                 if r.future.cancelled():
                     continue
+                # the launch's bytes with r in it: a backward anywhere in the launch
+                # allocates the backward part of every request it holds
+                cand = (LAUNCH_OVERHEAD + sum_f + r.fwd_bytes
+                        + ((sum_b + r.bwd_bytes) if (any_b or r.need_backward) else 0))
                 if (r.cls == cls and len(batch) < self.max_batch
-                        and self.bytes_in_flight + nbytes + r.footprint <= self.budget):
+                        and self.bytes_in_flight + cand <= self.budget):
                     batch.append(r)
-                    nbytes += r.footprint
+                    sum_f += r.fwd_bytes
+                    sum_b += r.bwd_bytes
+                    any_b = any_b or r.need_backward
+                    nbytes = cand
                 else:
                     kept.append(r)  # another class, or waits until memory frees up
             self.waiting = kept

@@ -110,11 +110,13 @@ class VarlenBatch:
         self.state = torch.zeros(max(1, off_state), dtype=torch.uint8, device=dev)
         self.status = torch.zeros(max(1, self.count), dtype=torch.int32, device=dev)
         self.iters = torch.zeros(max(1, self.count), dtype=torch.int32, device=dev)
-        self.grad = torch.zeros(self.base_in.shape, dtype=dtype, device=dev)
         fws, bws, _ = self.workspace_bytes()
         self.fws = torch.zeros(max(1, fws), dtype=torch.uint8, device=dev)
-        self.bws = torch.zeros(max(1, bws), dtype=torch.uint8, device=dev)
         self._fws_bytes, self._bws_bytes = fws, bws
+        # the gradient buffer (shaped like the inputs) and the adjoint workspace
+        # are allocated by the first backward() only
+        self.grad = None
+        self.bws = None
         self.offsets = [(descs[i].Q, descs[i].z, descs[i].lam, descs[i].nu) for i in range(self.count)]
 
     def workspace_bytes(self, opts=None):
@@ -136,12 +138,21 @@ class VarlenBatch:
         qb._check(rc, "qp_forward_varlen")
         return self
 
+    def backward_buffers(self):
+        """Allocate the gradient buffer (shaped like the inputs) and the packed
+        adjoint workspace, once."""
+        if self.grad is None:
+            self.grad = torch.zeros(self.base_in.shape, dtype=self.dtype, device=self.device)
+            self.bws = torch.zeros(max(1, self._bws_bytes), dtype=torch.uint8, device=self.device)
+        return self
+
     def backward(self, dl_dz: torch.Tensor, need: Optional[torch.Tensor] = None, opts=None):
         """dl_dz packed like z (concatenation of the problems' z); `need` an int32
         mask per problem (None = all).  Gradients land in self.grad, packed like
         the inputs."""
         o = opts if opts is not None else qb.default_opts(self.dtype)
         P = qb._ptr
+        self.backward_buffers()
         g = _to_device(dl_dz.to(dtype=self.dtype).contiguous(), self.device)
         self._dl = g
         self._need = None if need is None else \
@@ -158,14 +169,18 @@ class VarlenBatch:
         n, m, p = self.dims[i]
         oin, oz, ol, on = self.offsets[i]
         d = self.descs_host[i]
-        g = self.grad
-        return {
+        out = {
             "z": self.z[oz:oz + n], "lam": self.lam[ol:ol + m], "s": self.s[ol:ol + m],
             "nu": self.nu[on:on + p], "status": self.status[i], "iters": self.iters[i],
-            "dQ": g[d.Q:d.Q + n * n].view(n, n), "dq": g[d.q:d.q + n],
-            "dA": g[d.A:d.A + p * n].view(p, n), "db": g[d.b:d.b + p],
-            "dG": g[d.G:d.G + m * n].view(m, n), "dh": g[d.h:d.h + m],
         }
+        g = self.grad
+        if g is not None:
+            out.update({
+                "dQ": g[d.Q:d.Q + n * n].view(n, n), "dq": g[d.q:d.q + n],
+                "dA": g[d.A:d.A + p * n].view(p, n), "db": g[d.b:d.b + p],
+                "dG": g[d.G:d.G + m * n].view(m, n), "dh": g[d.h:d.h + m],
+            })
+        return out
 
     def result(self, i: int) -> Dict[str, np.ndarray]:
         return {k: (v.cpu().numpy() if v.dim() else int(v.item())) for k, v in self.views(i).items()}
@@ -187,12 +202,40 @@ class VarlenBatch:
         return host_t[:total].to(self.device, non_blocking=pinned)
 
 
+def problem_device_bytes(n: int, m: int, p: int, dtype: torch.dtype, backward: bool) -> int:
+    """Device bytes a VarlenBatch allocates for one problem of these dims: packed
+    inputs, outputs (z, lam, s, nu), the factor state (qp_state_bytes), status and
+    iters; with `backward` also its share of the gradient buffer (shaped like the
+    inputs) and of the packed adjoint workspace (nz + nineq + neq).  The
+    launch-wide forward workspace (one work-queue counter) is not included."""
+    esz = torch.finfo(dtype).bits // 8
+    inputs = n * n + n + p * n + p + m * n + m
+    total = esz * (inputs + n + 2 * m + p) + qb.state_bytes(dtype, n, m, p) + 8
+    if backward:
+        total += esz * (inputs + n + m + p)
+    return int(total)
+
+
+def allocated_bytes(vb: "VarlenBatch") -> int:
+    """Bytes of the device tensors a VarlenBatch holds now (inputs, outputs, state,
+    status, iters, descriptors, order, workspaces, gradients)."""
+    ts = [vb.base_in, vb.z, vb.lam, vb.s, vb.nu, vb.state, vb.status, vb.iters, vb.descs_dev,
+          vb.order, vb.fws, vb.grad, vb.bws]
+    return int(sum(t.numel() * t.element_size() for t in ts if t is not None))
+
+
 def capture_graph(vb: VarlenBatch, dl_dz: torch.Tensor, need: Optional[torch.Tensor] = None,
                   opts=None):
     """Capture forward + backward of an uneven batch into a HIP graph (torch.cuda.CUDAGraph).
     The launches read the batch's device buffers, so refreshing the inputs in place
     (vb.base_in, the dl_dz tensor) and replaying the graph re-solves.  The graph
-    holds kernel nodes only (the work-queue counter is cleared by a kernel)."""
+    holds kernel nodes only (the work-queue counter is cleared by a kernel).  A
+    host-side `need` mask is copied to the device before the capture, and the copy
+    is kept on `vb` for the graph's lifetime."""
+    if need is not None and need.device != vb.device:
+        need = need.to(dtype=torch.int32).contiguous().to(vb.device)
+        torch.cuda.synchronize()
+    vb._graph_need = need
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):

@@ -11,7 +11,7 @@ import pytest
 
 from paper_1703_00443_amd import synth
 
-from parity import TOL_G, g_err, grad_scale, oracle_grads, oracle_replay
+from parity import compare_problem, oracle_grads
 
 pytestmark = pytest.mark.gpu
 
@@ -65,8 +65,11 @@ def test_broadcast_parameters_sum_over_batch():
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_differentiation_workload_vs_oracle(dtype):
-    """128 QPs (nz=200, nineq=200, neq=50): gradients of one sampled problem
-    against the oracle at the replayed iterate."""
+    """128 QPs (nz=200, nineq=200, neq=50) through the autograd Function: z, s,
+    lambda, nu and the six gradients (whole and per tensor) of 16 problems spread
+    over the batch against the oracle at the replayed iterate."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     import torch
     from paper_1703_00443_amd.function import qp_layer
     b = synth.make_batch(**synth.DIFF_SCALE)
@@ -77,11 +80,23 @@ def test_differentiation_workload_vs_oracle(dtype):
     (z * torch.from_numpy(b.g.astype(dtype)).to(dev)).sum().backward()
     st = status.cpu().numpy()
     assert np.all((st == 0) | (st == 1) | (st == 4)), np.bincount(st)
-    i = 17
-    P = b.problem(i)
-    r = oracle_replay(P, int(iters[i]), dtype)
-    go = oracle_grads(P, r, P["g"], dtype)
-    scale = grad_scale(go)
-    for k, t in zip(("dQ", "dq", "dA", "db", "dG", "dh"), ins):
-        e = g_err(t.grad[i].detach().cpu().numpy().astype(np.float64), go[k], scale)
-        assert e <= TOL_G[dtype], (k, e)
+    # the forward's slacks are not an output of the layer: s = h - G z at the
+    # returned iterate plus its residual r_s, taken from the C ABI call below
+    from paper_1703_00443_amd import binding as qb
+    prob = qb.make_problem(*[t.detach() for t in ins])
+    fw = qb.forward(prob)
+    torch.cuda.synchronize()
+    assert torch.equal(fw.z, z.detach()) and torch.equal(fw.iters, iters)
+    idx = list(range(3, 128, 8))
+    assert len(idx) == 16
+
+    def one(i):
+        got = {"z": z[i].detach().cpu().numpy(), "lam": lam[i].detach().cpu().numpy(),
+               "nu": nu[i].detach().cpu().numpy(), "s": fw.s[i].cpu().numpy(),
+               "iters": int(iters[i])}
+        for k, t in zip(("dQ", "dq", "dA", "db", "dG", "dh"), ins):
+            got[k] = t.grad[i].detach().cpu().numpy()
+        return compare_problem(b.problem(i), got, dtype, tag="diff_%s[%d]" % (np.dtype(dtype).name, i))
+
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        list(ex.map(one, idx))

@@ -6,7 +6,8 @@ import pytest
 
 from paper_1703_00443_amd import synth
 
-from parity import TOL_G, TOL_Z, g_err, grad_scale, oracle_grads, oracle_replay, z_err
+from parity import (TOL_G, TOL_Z, compare_problem, g_err, grad_scale, log_margins, oracle_grads,
+                    oracle_replay, per_tensor_errors, z_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +30,8 @@ def _batch(dims, dtype, seed=90210, variants=None):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_mixed_sizes_vs_oracle(dtype):
+    """Every problem of a mixed batch: z, s, lambda, nu and all gradients against
+    the oracle replay."""
     import torch
     probs, vb = _batch(MIXED, dtype)
     dl = vb.pack_vectors([p["g"] for p in probs])
@@ -37,12 +40,7 @@ def test_mixed_sizes_vs_oracle(dtype):
     for i, P in enumerate(probs):
         r = vb.result(i)
         assert r["status"] in (0, 1, 4), (i, r["status"])
-        ref = oracle_replay(P, r["iters"], dtype)
-        assert z_err(r["z"], ref["z"]) <= TOL_Z[dtype], (i, MIXED[i])
-        go = oracle_grads(P, ref, P["g"], dtype)
-        sc = grad_scale(go)
-        for k in ("dQ", "dq", "dA", "db", "dG", "dh"):
-            assert g_err(r[k], go[k], sc) <= TOL_G[dtype], (i, MIXED[i], k)
+        compare_problem(P, r, dtype, tag="mixed_%s[%d]%s" % (np.dtype(dtype).name, i, MIXED[i]))
 
 
 def test_alone_equals_in_mix_bitwise():
@@ -109,7 +107,7 @@ def test_graph_replay_matches_eager():
 
 def test_uneven_workload_stratified_sample():
     """256 problems with nz ~ U{8..256}, nineq = 2 nz, neq ~ U{0..nz/4} (FP32): a
-    stratified sample of 12 problems against the oracle."""
+    stratified sample of 12 problems, every output against the oracle replay."""
     import torch
     dims = synth.varlen_dims(4096, 256)
     probs, vb = _batch(dims, np.float32, seed=4096)
@@ -122,22 +120,20 @@ def test_uneven_workload_stratified_sample():
     for i in order[:: len(order) // 12][:12]:
         P = probs[i]
         r = vb.result(int(i))
-        ref = oracle_replay(P, r["iters"], np.float32)
-        assert z_err(r["z"], ref["z"]) <= TOL_Z[np.float32], (i, dims[i])
+        compare_problem(P, r, np.float32, tag="uneven256[%d]%s" % (i, dims[i]), grads=False)
 
 
 def test_uneven_4096_stratified_256_vs_oracle():
     """The full 4096-problem uneven workload (FP32, nz ~ U{8..256}, nineq = 2 nz,
     neq ~ U{0..nz/4}, the benchmark's seed) in one launch; 256 problems spread
     evenly over the sizes checked against the oracle, which runs on a thread pool:
-      * z against the oracle replaying the GPU's iteration count;
-      * every gradient against the oracle's backward (eq. grads) at the iterate the
-        GPU returned, with h' = G z + s so that its system is the paper's K_sym of
-        that iterate.  The FP32 trajectory itself drifts from the FP64 replay, and
-        near constraints with both a small slack and a small multiplier the
-        gradient amplifies that drift past the tolerance; at a given iterate the
-        backward is well defined, and 37 of these 256 iterates have
-        cond(H) eps32 > 1, which the backward's FP64 projected CG must handle."""
+      * z, s, lambda, nu against the oracle replaying the GPU's iteration count;
+      * every gradient against the oracle's backward (eq. grads) at the replayed
+        iterate, and at the iterate the GPU returned with h' = G z + s so that its
+        system is the paper's K_sym of that iterate;
+      * problems that end STALLED: the distance of the returned z to the converged
+        solution (oracle at tol 1e-8 on the same cast inputs) and the KKT residual
+        of the returned iterate, bounded at 2e-2 and 10x the tolerance."""
     import os
     from concurrent.futures import ThreadPoolExecutor
     import torch
@@ -149,27 +145,57 @@ def test_uneven_4096_stratified_256_vs_oracle():
     torch.cuda.synchronize()
     st = vb.status[:vb.count].cpu().numpy()
     assert np.all((st == 0) | (st == 1) | (st == 4)), np.bincount(st)
+    log_margins("uneven4096_status", {"counts": np.bincount(st, minlength=5).tolist()})
     order = np.argsort([d[0] for d in dims], kind="stable")
     sample = [int(i) for i in order[::16]]
     assert len(sample) == 256
-    res = {i: vb.result(i) for i in sample}
+    stalled = [int(i) for i in np.nonzero(st == 4)[0]]
+    res = {i: vb.result(i) for i in set(sample) | set(stalled)}
     c = lambda x: None if x is None else np.asarray(x, dtype=np.float32).astype(np.float64)
+
+    def at_iterate(i):
+        P, r = probs[i], res[i]
+        Q, A, G, g = c(P["Q"]), c(P.get("A")), c(P.get("G")), c(P["g"])
+        z, lam, nu, s = (r[k].astype(np.float64) for k in ("z", "lam", "nu", "s"))
+        return oracle.backward(Q, A, G, G @ z + s, z, lam, nu, g)
 
     def check(i):
         P, r = probs[i], res[i]
         ref = oracle_replay(P, r["iters"], np.float32)
-        ez = z_err(r["z"], ref["z"])
-        Q, A, G, g = c(P["Q"]), c(P.get("A")), c(P.get("G")), c(P["g"])
-        z, lam, nu, s = (r[k].astype(np.float64) for k in ("z", "lam", "nu", "s"))
-        go = oracle.backward(Q, A, G, G @ z + s, z, lam, nu, g)
+        rec = compare_problem(P, r, np.float32, tag="uneven4096[%d]%s" % (i, dims[i]), grads=False,
+                              ref=ref)
+        go = at_iterate(i)
         sc = grad_scale(go)
         eg = max(g_err(r[k], go[k], sc) for k in ("dQ", "dq", "dA", "db", "dG", "dh"))
-        return i, ez, eg
+        gr = oracle_grads(P, ref, P["g"], np.float32)
+        er = max(g_err(r[k], gr[k], grad_scale(gr)) for k in ("dQ", "dq", "dA", "db", "dG", "dh"))
+        log_margins("uneven4096_grad[%d]%s" % (i, dims[i]),
+                    {"grad_at_iterate": float(eg), "grad_vs_replay": float(er),
+                     "pt_at_iterate": per_tensor_errors(r, go), "status": int(r["status"])})
+        return i, eg, er
+
+    def stalled_accuracy(i):
+        P, r = probs[i], res[i]
+        conv = oracle.solve(c(P["Q"]), c(P["q"]), c(P.get("A")), c(P.get("b")), c(P.get("G")),
+                            c(P.get("h")), tol=1e-8, max_iter=100)
+        Q, G, A = c(P["Q"]), c(P["G"]), c(P.get("A"))
+        z, lam, nu, s = (r[k].astype(np.float64) for k in ("z", "lam", "nu", "s"))
+        rx = 0.5 * (Q + Q.T) @ z + c(P["q"]) + G.T @ lam + (A.T @ nu if A is not None and A.size else 0)
+        rs = G @ z + s - c(P["h"])
+        kkt = max(np.abs(rx).max(), np.abs(rs).max(), float(s @ lam) / len(s))
+        rec = {"z_vs_converged": float(z_err(z, conv["z"])), "kkt": float(kkt),
+               "iters": int(r["iters"]), "oracle_status": int(conv["status"])}
+        log_margins("uneven4096_stalled[%d]%s" % (i, dims[i]), rec)
+        return rec
 
     with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
-        for i, ez, eg in ex.map(check, sample):
-            assert ez <= TOL_Z[np.float32], (i, dims[i], ez)
+        for i, eg, er in ex.map(check, sample):
             assert eg <= TOL_G[np.float32], (i, dims[i], eg)
+            assert er <= TOL_G[np.float32], (i, dims[i], er)
+        for rec in ex.map(stalled_accuracy, stalled):
+            # a STALLED iterate is the last one whose factorization succeeded:
+            # it is within a few times the tolerance of the KKT conditions
+            assert rec["kkt"] <= 10 * 1e-3 and rec["z_vs_converged"] <= 2e-2, rec
 
 
 def test_unit_row_flag_is_accepted_and_dense_in_uneven_batches():

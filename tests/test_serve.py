@@ -10,7 +10,8 @@ import pytest
 
 import oracle
 from paper_1703_00443_amd import synth
-from paper_1703_00443_amd.serve import RejectedError, Server, footprint_bytes, percentiles
+from paper_1703_00443_amd.serve import (LAUNCH_OVERHEAD, RejectedError, Server, footprint_bytes,
+                                        footprint_parts, percentiles)
 
 
 class FakeBackend:
@@ -89,8 +90,8 @@ def test_oversized_request_is_rejected():
 
 def test_budget_bounds_bytes_in_flight_and_queues_the_rest():
     probs, dims = _problems(20)
-    fps = [footprint_bytes(d[0], d[1], d[2], 8, False) for d in dims]
-    budget = 3 * max(fps)  # room for about three requests at a time
+    fps = [footprint_parts(d[0], d[1], d[2], 8)[0] for d in dims]
+    budget = LAUNCH_OVERHEAD + 3 * max(fps)  # room for about three requests at a time
     be = FakeBackend(0.03)
     srv = Server(backend=be, hbm_budget=budget, max_inflight=4, class_bounds=())
     futs = [srv.submit(P) for P in probs]
@@ -188,3 +189,45 @@ def test_large_burst_leaves_slots_for_small_requests():
     srv.close()
     assert t_small < 0.3 + 0.2   # one device duration, not a wait behind the burst
     assert srv.stats["launches_per_class"] == [1, 8]
+
+
+def test_state_bytes_mirror_matches_library():
+    """The server's host copy of the state layout equals qp_state_bytes."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd.serve import state_bytes_host
+    for dt, esz in ((torch.float32, 4), (torch.float64, 8)):
+        for n, m, p in [(1, 0, 0), (1, 3, 0), (10, 20, 5), (16, 16, 0), (17, 40, 3), (100, 100, 0),
+                        (255, 510, 63), (512, 1024, 64), (1024, 4096, 1000)]:
+            assert state_bytes_host(esz, n, m, p) == qb.state_bytes(dt, n, m, p), (dt, n, m, p)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_footprint_covers_what_a_launch_allocates(seed):
+    """batch_bytes over a launch's requests bounds the device bytes VarlenBatch
+    allocates for it (every tensor rounded up to the allocator's 512-byte blocks),
+    with and without a backward in the launch, and equals a forward-only launch's
+    request bytes when no request asks for a backward."""
+    import torch
+    from paper_1703_00443_amd import synth
+    from paper_1703_00443_amd.serve import Request, batch_bytes, footprint_parts
+    from paper_1703_00443_amd.varlen import VarlenBatch
+    rng = np.random.default_rng(seed)
+    dims = synth.serving_dims(100 + seed, 12)
+    probs = synth.make_varlen(100 + seed, [d[:3] for d in dims], dtype=np.float32)
+    for mode in ("none", "some"):
+        reqs = []
+        for P, d in zip(probs, dims):
+            fb, bb = footprint_parts(d[0], d[1], d[2], 4)
+            nb = mode == "some" and bool(rng.uniform() < 0.3)
+            reqs.append(Request(P, nb, None, fb, 0.0, dims=d[:3], fwd_bytes=fb, bwd_bytes=bb))
+        if mode == "some":
+            reqs[0].need_backward = True
+        vb = VarlenBatch(probs, dtype=torch.float32, device=torch.device("cpu"))
+        if any(r.need_backward for r in reqs):
+            vb.backward_buffers()
+        ts = [vb.base_in, vb.z, vb.lam, vb.s, vb.nu, vb.state, vb.status, vb.iters, vb.descs_dev,
+              vb.order, vb.fws, vb.grad, vb.bws]
+        alloc = sum((t.numel() * t.element_size() + 511) // 512 * 512 for t in ts if t is not None)
+        assert batch_bytes(reqs) >= alloc, (mode, batch_bytes(reqs), alloc)
+        assert batch_bytes(reqs) <= 1.05 * alloc + 16384, (mode, batch_bytes(reqs), alloc)
