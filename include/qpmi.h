@@ -177,6 +177,25 @@ int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims dims, const q
                             void *dq, void *dA, void *db, void *dG, void *dh, void *ws,
                             size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): qp_backward_batched
+ * without a workspace argument, computing the same results with the same
+ * kernels.  The adjoint vectors live in a library-owned static device array of
+ * QP_NOALLOC_SCRATCH_BYTES on each GPU, present from the time the library's
+ * code object is loaded on that GPU until the process ends; the call allocates
+ * and frees nothing.  Returns QP_EWS when the backward's workspace
+ * (qp_workspace_query) exceeds that size (e.g. more than 4096 FP64 problems with
+ * nz + nineq + neq <= 512), QP_EHIP when the array's device address cannot be
+ * obtained.  Every call on one GPU uses the same array, and its contents are
+ * the last call's: calls that overlap in time on one GPU (from several streams
+ * or threads) race and must be serialised by the caller. */
+#define QP_NOALLOC_SCRATCH_BYTES (16u << 20)
+int32_t qp_backward_batched_noalloc(qp_dtype dtype, int32_t batch, qp_dims dims,
+                                    const qp_data *data, const qp_opts *opts, const void *z,
+                                    const void *lam, const void *nu, const void *s,
+                                    const void *state, const void *dl_dz, void *dQ, void *dq,
+                                    void *dA, void *db, void *dG, void *dh, void *stream);
+
 /* ---- uneven batches ------------------------------------------------------------ */
 
 /* One problem of an uneven batch.  All offsets are in elements of the dtype

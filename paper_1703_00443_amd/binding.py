@@ -52,8 +52,9 @@ class qp_problem_desc(ctypes.Structure):
 
 
 EXPORTED = ("qp_default_opts", "qp_state_bytes", "qp_workspace_query", "qp_forward_batched",
-            "qp_backward_batched", "qp_varlen_workspace_query", "qp_forward_varlen",
-            "qp_backward_varlen", "qp_plan", "qp_last_hip_error", "qp_version")
+            "qp_backward_batched", "qp_backward_batched_noalloc", "qp_varlen_workspace_query",
+            "qp_forward_varlen", "qp_backward_varlen", "qp_plan", "qp_last_hip_error", "qp_version")
+NOALLOC_SCRATCH_BYTES = 16 << 20  # QP_NOALLOC_SCRATCH_BYTES
 
 _lib = None
 
@@ -76,6 +77,8 @@ def load_library(path: str = LIB_PATH):
                                        vp, vp, vp, vp, sz, vp]
     lib.qp_backward_batched.argtypes = [i32, i32, qp_dims, P(qp_data), P(qp_opts), vp, vp, vp, vp,
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.qp_backward_batched_noalloc.argtypes = [i32, i32, qp_dims, P(qp_data), P(qp_opts), vp, vp, vp,
+                                                vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.qp_varlen_workspace_query.argtypes = [i32, i32, vp, P(qp_opts), P(sz), P(sz), P(sz)]
     lib.qp_forward_varlen.argtypes = [i32, i32, vp, vp, vp, vp, P(qp_opts), vp, vp, vp, vp, vp, vp,
                                       vp, vp, sz, vp]
@@ -280,4 +283,30 @@ def backward(prob: Problem, fwd: ForwardResult, dl_dz: torch.Tensor, opts: Optio
                                  _ptr(dl_dz), _ptr(g.dQ), _ptr(g.dq), _ptr(g.dA), _ptr(g.db), _ptr(g.dG),
                                  _ptr(g.dh), _ptr(ws), bws, _stream())
     _check(rc, "qp_backward_batched")
+    return g
+
+
+def backward_noalloc(prob: Problem, fwd: ForwardResult, dl_dz: torch.Tensor,
+                     opts: Optional[qp_opts] = None, out: Optional[Grads] = None) -> Grads:
+    """qp_backward_batched_noalloc on the current stream: the library allocates
+    nothing (its adjoint workspace is a static device array).  The gradient
+    tensors are the caller's: pass `out` to reuse them."""
+    lib = load_library()
+    dt = prob.Q.dtype
+    B, n, m, p = prob.batch, prob.n, prob.m, prob.p
+    o = opts if opts is not None else default_opts(dt)
+    dev = prob.Q.device
+    dl_dz = dl_dz.to(dtype=dt).contiguous()
+    if out is None:
+        mk = lambda *shape: torch.empty(*shape, dtype=dt, device=dev)
+        out = Grads(mk(B, n, n), mk(B, n), mk(B, p, n) if p else None, mk(B, p) if p else None,
+                    mk(B, m, n) if m else None, mk(B, m) if m else None)
+    d = prob.data()
+    g = out
+    rc = lib.qp_backward_batched_noalloc(dtype_code(dt), B, qp_dims(n, m, p), ctypes.byref(d),
+                                         ctypes.byref(o), _ptr(fwd.z), _ptr(fwd.lam), _ptr(fwd.nu),
+                                         _ptr(fwd.s), _ptr(fwd.state), _ptr(dl_dz), _ptr(g.dQ),
+                                         _ptr(g.dq), _ptr(g.dA), _ptr(g.db), _ptr(g.dG), _ptr(g.dh),
+                                         _stream())
+    _check(rc, "qp_backward_batched_noalloc")
     return g

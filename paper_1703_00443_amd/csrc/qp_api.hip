@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -11,6 +12,38 @@
 using namespace qpmi;
 
 static thread_local int32_t g_last_hip_error = 0;
+
+// Adjoint workspace of qp_backward_batched_noalloc: a static device array, one
+// copy per GPU, held until the process ends.  Host code never passes its name
+// to a kernel (on the host it is a stand-in, not a device address): the
+// device address of each GPU's copy is looked up once with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[QP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// The device address of the current GPU's scratch array (nullptr on failure,
+// with the HIP error recorded).
+static void *scratch_address() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        g_last_hip_error = (int32_t)(e != hipSuccess ? e : hipErrorInvalidDevice);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_last_hip_error = (int32_t)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
 
 static int esize(qp_dtype dt) { return dt == QP_F64 ? 8 : 4; }
 static bool dtype_ok(qp_dtype dt) { return dt == QP_F32 || dt == QP_F64; }
@@ -198,6 +231,25 @@ int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_d
     L.lds_limit = lim;
     L.max_rows = d.nz + d.nineq + d.neq + 1;
     return hip_ret(launch_backward(dtype, L, (hipStream_t)stream));
+}
+
+int32_t qp_backward_batched_noalloc(qp_dtype dtype, int32_t batch, qp_dims d, const qp_data *x,
+                                    const qp_opts *opts, const void *z, const void *lam,
+                                    const void *nu, const void *s, const void *state,
+                                    const void *dl_dz, void *dQ, void *dq, void *dA, void *db,
+                                    void *dG, void *dh, void *stream) {
+    if (!dtype_ok(dtype)) return QP_EDTYPE;
+    if (batch < 0 || !dims_ok(d)) return QP_EARG;
+    if (batch == 0) return check_opts(opts);
+    size_t need = 0;
+    qp_workspace_query(dtype, batch, d, opts, nullptr, &need);
+    if (need > (size_t)QP_NOALLOC_SCRATCH_BYTES) return QP_EWS;
+    void *ws = scratch_address();
+    if (!ws) return QP_EHIP;
+    // every adjoint entry of every problem is written by the solve kernel before
+    // the gradient kernel reads it: nothing has to start at zero
+    return qp_backward_batched(dtype, batch, d, x, opts, z, lam, nu, s, state, dl_dz, dQ, dq, dA,
+                               db, dG, dh, ws, (size_t)QP_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 // ---- uneven batches ----------------------------------------------------------
