@@ -89,7 +89,8 @@ typedef struct {
 /* Flags of qp_opts.flags.
  * QP_FLAG_G_UNIT_ROWS: every row of G is a signed unit vector (one entry +1 or
  *   -1, the rest 0), as for bounds z_j <= h_k or -z_j <= h_k (the box and
- *   non-negativity layers of Section 4).  G is still passed densely.  The
+ *   non-negativity constraints of the Sudoku layer, Section 4.4, and of
+ *   the ReLU layer in the proof of Theorem 2).  G is still passed densely.  The
  *   register-tile policy then forms G^T D G as a diagonal and applies G by
  *   gathers instead of products; a problem whose G does not have the structure
  *   (checked in the kernel) is solved by the dense path.  Results equal the

@@ -196,6 +196,75 @@ __device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int row
     }
 }
 
+// The largest row 1-norm max_r sum_{c<cols} |M[r][c]|, returned to every
+// thread: 16 lanes per row as in mv_rows (coalesced, four loads in flight).
+template <typename T, int NT>
+__device__ __forceinline__ T max_row_abs_sum(const T *__restrict__ M, int ld, int rows, int cols, T *red) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+    T mx = 0;
+    for (int r0 = 4 * w; r0 < rows; r0 += 4 * NW) {
+        const int r = r0 + g < rows ? r0 + g : rows - 1;
+        const T *row = M + (size_t)r * ld;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int c = cl;
+        for (; c + 48 < cols; c += 64) {
+            a0 += fabs(row[c]);
+            a1 += fabs(row[c + 16]);
+            a2 += fabs(row[c + 32]);
+            a3 += fabs(row[c + 48]);
+        }
+        for (; c < cols; c += 16) a0 += fabs(row[c]);
+        mx = fmax(mx, row16_sum((a0 + a1) + (a2 + a3)));
+    }
+    T d0 = 0, d1 = 0;
+    block_reduce3<T, NT>(d0, mx, d1, red);
+    return mx;
+}
+
+// The largest column 1-norm max_c sum_{r<rows} |M[r][c]|, returned to every
+// thread: the rows are split into groups of threads (coalesced rows, eight
+// loads in flight) as far as `cap` entries of `scratch` hold their partial sums,
+// which are added in a fixed order.
+template <typename T, int NT>
+__device__ __forceinline__ T max_col_abs_sum(const T *__restrict__ M, int ld, int rows, int cols, T *scratch,
+                                             int cap, T *red) {
+    const int ng = cols > 0 ? max(1, min(min(NT, cap) / cols, 8)) : 1;
+    const int chunk = (rows + ng - 1) / ng;
+    T mx = 0;
+    for (int t = threadIdx.x; t < ng * cols; t += NT) {
+        const int q = t / cols, i = t - q * cols;
+        const int k0 = q * chunk, k1 = min(rows, k0 + chunk);
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0;
+        int k = k0;
+        for (; k + 7 < k1; k += 8) {
+            a0 += fabs(M[(size_t)k * ld + i]);
+            a1 += fabs(M[(size_t)(k + 1) * ld + i]);
+            a2 += fabs(M[(size_t)(k + 2) * ld + i]);
+            a3 += fabs(M[(size_t)(k + 3) * ld + i]);
+            a4 += fabs(M[(size_t)(k + 4) * ld + i]);
+            a5 += fabs(M[(size_t)(k + 5) * ld + i]);
+            a6 += fabs(M[(size_t)(k + 6) * ld + i]);
+            a7 += fabs(M[(size_t)(k + 7) * ld + i]);
+        }
+        for (; k < k1; ++k) a0 += fabs(M[(size_t)k * ld + i]);
+        const T r = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+        if (ng > 1) scratch[t] = r;
+        else mx = fmax(mx, r);
+    }
+    if (ng > 1) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < cols; i += NT) {
+            T acc = scratch[i];
+            for (int q = 1; q < ng; ++q) acc += scratch[q * cols + i];
+            mx = fmax(mx, acc);
+        }
+    }
+    T d0 = 0, d1 = 0;
+    block_reduce3<T, NT>(d0, mx, d1, red);
+    return mx;
+}
+
 // out[i] = sum_{k<rows} M[k][i] v[k] for i < cols.  When cols < NT the rows
 // are split into up to eight groups whose partial sums (scratch, NT entries)
 // are added in a fixed order; otherwise one thread per column.

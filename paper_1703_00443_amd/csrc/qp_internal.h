@@ -28,9 +28,8 @@ __host__ __device__ constexpr int u_ld(int n) { return (n + 15) & ~15; }
 //   D   [nineq]      lambda / s at the returned iterate
 //   Wt  [neq*nz]     Wt = (L^{-1} A^T)^T
 //   US  [neq*neq]    upper triangle = LS^{-T}, LS LS^T = Wt Wt^T (Schur complement)
-//   gw  [nineq]      forward scratch: the 1-norms of the rows of G
 struct StateLayout {
-    size_t off_valid, off_U, off_D, off_Wt, off_US, off_gw, bytes;
+    size_t off_valid, off_U, off_D, off_Wt, off_US, bytes;
 };
 
 __host__ __device__ inline StateLayout state_layout(int esz, int n, int m, int p) {
@@ -41,7 +40,6 @@ __host__ __device__ inline StateLayout state_layout(int esz, int n, int m, int p
     s.off_D = o; o += align_up((size_t)(m > 0 ? m : 1) * esz, kAlignBytes);
     s.off_Wt = o; o += align_up((size_t)(p > 0 ? p * n : 1) * esz, kAlignBytes);
     s.off_US = o; o += align_up((size_t)(p > 0 ? p * p : 1) * esz, kAlignBytes);
-    s.off_gw = o; o += align_up((size_t)(m > 0 ? m : 1) * esz, kAlignBytes);
     s.bytes = o;
     return s;
 }

@@ -138,8 +138,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     int st = QP_STATUS_MAX_ITER, it = 0;
     bool stalled = false;  // re-running the previous iterate after a breakdown
     constexpr T kEps = sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
-    T *gw = reinterpret_cast<T *>(P.state + state_layout(sizeof(T), n, m, p).off_gw);
-    T gcol = 0;
+    T gnorm = 0;
     if (!fin) {
         st = QP_STATUS_NONFINITE;
         for (int e = tid; e < n; e += NT) z[e] = 0;
@@ -153,21 +152,12 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     // Row 1-norms of G (state scratch) and the largest column 1-norm: they bound
     // how much the rounding of G dz, multiplied by D = lambda / s when the
     // multiplier step is recovered, can leave in the first Newton row (below).
-    {
-        for (int k = tid; k < m; k += NT) {
-            T a = 0;
-            for (int j = 0; j < n; ++j) a += fabs(PG[(size_t)k * n + j]);
-            gw[k] = a;
-        }
-        for (int j = tid; j < n; j += NT) {
-            T a = 0;
-            for (int k = 0; k < m; ++k) a += fabs(PG[(size_t)k * n + j]);
-            gcol = fmax(gcol, a);
-        }
-        T d0 = 0, d1 = pinf<T>();
-        block_reduce3<T, NT>(d0, gcol, d1, red);  // its barriers also publish gw
-    }
-
+    // The product of the largest row and column 1-norms of G: with eps |dz|
+    // max D it bounds what the rounding of G dz, multiplied by D = lambda / s
+    // when the multiplier step is recovered, can leave in the first Newton row.
+    // (The iteration's vectors are idle until the initial point: their space
+    // holds the partial column sums.)
+    gnorm = max_row_abs_sum<T, NT>(PG, n, m, n, red) * max_col_abs_sum<T, NT>(PG, n, m, n, sm, Lo.red, red);
     // ---- initial point: K with the (D(lambda), D(s)) pair replaced by (I, I)
     for (int e = tid; e < m; e += NT) D[e] = T(1);
     __syncthreads();
@@ -223,7 +213,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             mv_cols<T, NT>(A, n, p, n, nu, tn2);  // A^T nu
             __syncthreads();
         }
-        T vsum = 0, vmax = 0, vmin = pinf<T>();
+        T vsum = 0, vmax = 0, vmin = pinf<T>(), emax = 0;
         for (int i = tid; i < n; i += NT) {
             T acc = tn[i] + Pq[i] + rx[i];
             if (p > 0) acc += tn2[i];
@@ -237,7 +227,9 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             vmax = fmax(vmax, fabs(r));
             vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
             vsum += s[k] * lam[k];
-            D[k] = lam[k] / s[k];
+            const T dk = lam[k] / s[k];
+            D[k] = dk;
+            emax = fmax(emax, dk);
         }
         for (int k = tid; k < p; k += NT) {
             const T r = -(ry[k] - Pb[k]);
@@ -245,7 +237,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             vmax = fmax(vmax, fabs(r));
             vmin = fmin(vmin, isfinite(r) ? T(1) : T(0));
         }
-        block_reduce3<T, NT>(vsum, vmax, vmin, red);
+        block_reduce4<T, NT>(vsum, vmax, emax, vmin, red);
         const T mu = vsum / T(m);
         const T err = fmax(mu, vmax);
         const bool finite_now = vmin > T(0) && isfinite(mu);
@@ -311,7 +303,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         fac.g_mv(dzc, tm);
         // combined direction (dz in dza, dnu in dna, ds in tm, dlam in w)
         amin = pinf<T>(); d0 = 0;
-        T emax = 0, dzmax = 0;
+        T dzmax = 0;
         for (int k = tid; k < m; k += NT) {
             const T dsc_k = -tm[k];
             const T dlc_k = w[k] - D[k] * dsc_k;
@@ -321,7 +313,6 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             dlc[k] = dl;
             if (ds < T(0)) amin = fmin(amin, -s[k] / ds);
             if (dl < T(0)) amin = fmin(amin, -lam[k] / dl);
-            emax = fmax(emax, D[k] * gw[k]);
         }
         for (int i = tid; i < n; i += NT) {
             const T dz = dza[i] + dzc[i];
@@ -329,16 +320,17 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             dzmax = fmax(dzmax, fabs(dz));
         }
         for (int k = tid; k < p; k += NT) dna[k] += dnc[k];
-        block_reduce4<T, NT>(d0, emax, dzmax, amin, red);
+        block_reduce3<T, NT>(d0, dzmax, amin, red);
 
         // One step of iterative refinement of the combined direction on the
         // residual of the unreduced Newton system, with the same factor, when
-        // the bound eps |dz| max_k(D_k |G_k|_1) max_j |G^T e_j|_1 on the error
-        // that recovering dlam = c + D G dz leaves in the first row reaches a
-        // quarter of the tolerance (large D near the end of the solve).  Without
-        // it the dual residual can grow from one iterate to the next there
-        // instead of shrinking with the step.
-        if (kEps * dzmax * emax * gcol >= T(0.25) * tol) {
+        // the error that recovering dlam = c + D G dz can leave in the first row
+        // may reach a quarter of the tolerance (large D near the end of the
+        // solve).  The bound eps |dz| max_k D_k max_k |G_k|_1 max_j |G^T e_j|_1
+        // overestimated the error seen in the dual residual by about 10x, hence
+        // the test against 2.5 tol.  Without it the dual residual can grow from
+        // one iterate to the next there instead of shrinking with the step.
+        if (kEps * dzmax * emax * gnorm >= T(2.5) * tol) {
             // e2 = (sigma mu - s lam - dsa dla) - (lam ds + s dl)        -> dla
             for (int k = tid; k < m; k += NT)
                 dla[k] = (sigma * mu - s[k] * lam[k] - dsa[k] * dla[k]) - (lam[k] * dsc[k] + s[k] * dlc[k]);

@@ -198,9 +198,8 @@ __device__ __forceinline__ unsigned group_bcast(unsigned v) {  // row SG of 16 l
 template <int SRC, typename T>
 __device__ __forceinline__ T row_bcast16(T v) {
     if constexpr (sizeof(T) == 8) {
-        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-        const unsigned lo = row_bcast16<SRC>((unsigned)u), hi = row_bcast16<SRC>((unsigned)(u >> 32));
-        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+        // one 64-bit DPP move (row_newbcast is a DPP64 control on gfx950)
+        return __builtin_amdgcn_update_dpp(T(0), v, 0x150 + SRC, 0xf, 0xf, false);
     } else {
         return __builtin_bit_cast(T, row_bcast16<SRC>(__builtin_bit_cast(unsigned, v)));
     }

@@ -59,13 +59,12 @@ class Request:
 
 def state_bytes_host(esz: int, n: int, m: int, p: int) -> int:
     """qp_state_bytes without the library: the validity word, then U (leading
-    dimension nz rounded up to 16), D, Wt, US and the row norms of G, each
-    region 256-byte aligned.
+    dimension nz rounded up to 16), D, Wt and US, each region 256-byte aligned.
     A CPU test checks it against the library's answer."""
     al = lambda v: (v + 255) // 256 * 256
     ld = (n + 15) & ~15
     return int(256 + al(ld * ld * esz) + al(max(m, 1) * esz) + al((p * n if p else 1) * esz)
-               + al((p * p if p else 1) * esz) + al(max(m, 1) * esz))
+               + al((p * p if p else 1) * esz))
 
 
 def footprint_parts(n: int, m: int, p: int, esz: int):

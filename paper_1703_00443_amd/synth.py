@@ -2,7 +2,7 @@
 
 Shared by the tests (which feed the same arrays to the HIP path and to the
 oracle), the bench and the serving demo.  The recipe follows the paper's timing
-experiment (Section 5.1, its footnote: Q = U^T U + 1e-3 I, G normal, h = G z0 + s0
+experiment (Section 4.1, its footnote: Q = U^T U + 1e-3 I, G normal, h = G z0 + s0
 with z0 normal and s0 uniform so that every problem is feasible) and the MNIST
 layer parametrisation (Appendix A: Q = L L^T + eps I, b = A z0, h = G z0 + s0):
 
@@ -74,7 +74,7 @@ def make_batch(seed: int, B: int, n: int, m: int, p: int, row_normalize: bool = 
 
 def box_batch(seed: int, B: int, n: int, dtype=np.float64) -> QPBatch:
     """Box-constrained QPs l <= z <= u (the bound constraints of the paper's
-    box and ReLU layers, Section 4): G = [I; -I], h = [u; -l] with
+    ReLU layer in the proof of Theorem 2, z >= 0, and box bounds): G = [I; -I], h = [u; -l] with
     u ~ U(0.5, 1.5), l ~ -U(0.5, 1.5); Q, q and dl/dz as above (q scaled by 3
     so that a good share of the bounds is active).  Problem i uses
     default_rng([seed, i])."""

@@ -252,7 +252,7 @@ def test_kkt_invariants(cfg):
 
 
 def test_row_scaling_invariance():
-    """Section 4 (limitations): scaling a row of (G, h) by c > 0 leaves z* unchanged;
+    """Section 3.3 (limitations): scaling a row of (G, h) by c > 0 leaves z* unchanged;
     lambda_i scales by 1/c."""
     rng = np.random.default_rng(8)
     Q, q, A, b, G, h, _ = synth.one_problem(rng, 8, 12, 2)
