@@ -3,6 +3,7 @@
     python -m paper_1703_00443_amd.profiling stats  <run_kernel_stats.csv>
     python -m paper_1703_00443_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> --kernel qp_forward_kernel --calib-bytes N
+    python -m paper_1703_00443_amd.profiling util <counter_collection.csv> --kernel K --active-cus C
 
 `stats` prints the kernel-time table as markdown.  `traffic` computes HBM bytes
 per dispatch of a kernel from two --pmc runs (FETCH_SIZE, then WRITE_SIZE, both
@@ -62,6 +63,44 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, calib_bytes: int):
             "write_bytes": write, "hbm_bytes_per_launch": fetch + write}
 
 
+def utilization(counter_csv: str, kernel: str, active_cus: int, total_cus: int = 256, xcds: int = 8,
+                simds_per_cu: int = 4):
+    """MFMA and VALU busy fractions of one kernel from a --pmc run that holds
+    SQ_VALU_MFMA_BUSY_CYCLES, SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES, GRBM_GUI_ACTIVE
+    and the MFMA / VALU instruction counters.  Definitions follow rocprofv3's
+    derived metrics (MfmaUtil, VALUBusy), with GRBM_GUI_ACTIVE summed over the
+    XCDs divided by their number; the '_active' figures divide by the CUs that
+    held work (one workgroup per CU)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    name = None
+    for r in csv.DictReader(open(counter_csv)):
+        if kernel in r["Kernel_Name"]:
+            name = r["Kernel_Name"]
+            per[int(r["Dispatch_Id"])][r["Counter_Name"]] += float(r["Counter_Value"])
+    if not per:
+        raise SystemExit("kernel %s not found" % kernel)
+    steady = [per[d] for d in sorted(per)][1:] or [per[d] for d in sorted(per)]
+    med = {k: statistics.median(v[k] for v in steady) for k in steady[0]}
+    gui = med["GRBM_GUI_ACTIVE"] / xcds
+    out = {"kernel": name, "dispatches": len(steady), "gpu_cycles": gui}
+    mf = med.get("SQ_VALU_MFMA_BUSY_CYCLES")
+    if mf is not None:
+        out["mfma_busy_chip"] = mf / (total_cus * simds_per_cu * gui)
+        out["mfma_busy_active"] = mf / (active_cus * simds_per_cu * gui)
+    va = med.get("SQ_ACTIVE_INST_VALU")
+    if va is not None:
+        out["valu_busy_chip"] = va / (total_cus * gui)
+        out["valu_busy_active"] = va / (active_cus * gui)
+    for k in ("SQ_INSTS_MFMA", "SQ_INSTS_VALU", "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+              "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32", "SQ_BUSY_CU_CYCLES"):
+        if k in med:
+            out[k] = med[k]
+    for k, f in (("SQ_INSTS_VALU_MFMA_MOPS_F64", 512), ("SQ_INSTS_VALU_MFMA_MOPS_F32", 512)):
+        if k in med:
+            out["mfma_flops_per_launch"] = med[k] * f
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -72,7 +111,15 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--kernel", required=True)
     b.add_argument("--calib-bytes", type=int, required=True)
+    c = sub.add_parser("util")
+    c.add_argument("csv")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--active-cus", type=int, required=True)
     args = ap.parse_args()
+    if args.cmd == "util":
+        for k, v in utilization(args.csv, args.kernel, args.active_cus).items():
+            print("%s: %s" % (k, ("%.6g" % v) if isinstance(v, float) else v))
+        return
     if args.cmd == "stats":
         print(kernel_stats_markdown(args.csv))
     else:

@@ -75,3 +75,42 @@ def test_served_fp64_results_equal_alone_results():
         if i % 5 == 0:
             ref = oracle_replay(P, res[i]["iters"], np.float64)
             assert z_err(res[i]["z"], ref["z"]) <= TOL_Z[np.float64]
+
+
+def test_served_large_requests_equal_alone_results():
+    """Requests with nz up to 512 (the streamed-tile policy above 256 in FP32)
+    in the mix: 24 requests, half with a backward, each result bitwise equal to
+    the request solved alone, and every output of three of them against the oracle."""
+    import torch
+    from paper_1703_00443_amd.serve import Server
+    from paper_1703_00443_amd.varlen import VarlenBatch
+    from paper_1703_00443_amd import binding as qb
+    dims = synth.serving_dims(57, 24, n_lo=200, n_hi=512)
+    assert max(d[0] for d in dims) > 256
+    assert any(qb.plan(torch.float32, *d[:3])[0] == qb.VARIANT_STREAM for d in dims)
+    probs = synth.make_varlen(57, [d[:3] for d in dims], dtype=np.float32)
+    srv = Server(dtype=torch.float32, hbm_budget=1 << 30, max_inflight=4)
+    futs = [srv.submit(P, need_backward=d[3], dl_dz=P["g"] if d[3] else None) for P, d in zip(probs, dims)]
+    res = [f.result(timeout=300) for f in futs]
+    srv.close()
+    assert srv.stats["admitted"] == len(probs)
+    for i, P in enumerate(probs):
+        one = VarlenBatch([P], dtype=torch.float32, table=srv.backend.table)
+        one.forward()
+        if dims[i][3]:
+            one.backward(one.pack_vectors([P["g"]]))
+        torch.cuda.synchronize()
+        a = one.result(0)
+        for k in ("z", "lam", "nu", "s"):
+            np.testing.assert_array_equal(res[i][k], a[k], err_msg="%d %s" % (i, k))
+        if dims[i][3]:
+            for k in ("dQ", "dG", "dh"):
+                np.testing.assert_array_equal(res[i][k], a[k], err_msg="%d %s" % (i, k))
+    # the oracle (unreduced LU of size nz + 2 nineq + neq) on the three smallest
+    # requests, two of them with a backward
+    from parity import compare_problem
+    order = sorted(range(len(dims)), key=lambda i: dims[i][0] + 2 * dims[i][1])
+    picked = [i for i in order if dims[i][3]][:2] + [i for i in order if not dims[i][3]][:1]
+    for i in picked:
+        compare_problem(probs[i], dict(res[i]), np.float32, tag="serve_large[%d]%s" % (i, dims[i][:3]),
+                        grads=bool(dims[i][3]))
