@@ -304,7 +304,7 @@ def bench_serving(args):
     return out
 
 
-def time_uniform(B, n, m, p, dtype, steps, warmup=2, seed=1100, serial=False):
+def time_uniform(B, n, m, p, dtype, steps, warmup=2, seed=1100, serial=False, variant=0):
     """Forward / backward milliseconds per call of one uniform batch of the
     paper's generator (row-normalised G), HIP events on the launch stream; with
     `serial`, also the same B problems as B batch-1 calls with a host sync each."""
@@ -318,7 +318,7 @@ def time_uniform(B, n, m, p, dtype, steps, warmup=2, seed=1100, serial=False):
     T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(npdt))).to(dev)
     prob = qb.make_problem(T(bnp.Q), T(bnp.q), None, None, T(bnp.G), T(bnp.h))
     g = T(bnp.g)
-    opts = qb.default_opts(tdt)
+    opts = qb.default_opts(tdt, variant=variant)
     fw = qb.forward(prob, opts)
     ws = torch.empty(max(1, qb.workspace_bytes(tdt, B, n, m, p, opts)[1]), dtype=torch.uint8, device=dev)
     for _ in range(warmup):
@@ -336,7 +336,8 @@ def time_uniform(B, n, m, p, dtype, steps, warmup=2, seed=1100, serial=False):
     torch.cuda.synchronize()
     out = {"fwd_ms": round(float(np.mean([a.elapsed_time(b) for a, b, _ in ev])), 4),
            "bwd_ms": round(float(np.mean([b.elapsed_time(c) for _, b, c in ev])), 4),
-           "iters_mean": round(float(fw.iters.float().mean().item()), 3)}
+           "iters_mean": round(float(fw.iters.float().mean().item()), 3),
+           "status_counts": np.bincount(fw.status.cpu().numpy(), minlength=5).tolist()}
     if serial:
         singles = [qb.make_problem(prob.Q[i:i + 1], prob.q[i:i + 1], None, None, prob.G[i:i + 1],
                                    prob.h[i:i + 1]) for i in range(B)]
@@ -396,13 +397,14 @@ def bench_sweep(args):
     the same problems solved one per call (host sync per call, up to 128)."""
     steps = args.steps if args.steps != 20 else 10   # the paper averages 10 trials
     dts = (args.dtype,) if args.dtype_given else ("f64", "f32")
+    parts = set(args.sweep_parts.split(","))
     rows_size, rows_batch = [], []
     for dt in dts:
-        for n in (10, 50, 100, 500):
+        for n in ((10, 50, 100, 500) if "size" in parts else ()):
             r = time_uniform(128, n, n, 0, dt, steps, seed=1100 + n)
             rows_size.append({"dtype": dt, "batch": 128, "nz": n, "nineq": n, **r})
             print("sweep size %s nz=%d: %s" % (dt, n, r), file=sys.stderr, flush=True)
-        for B in (1, 8, 32, 128, 512, 2048):
+        for B in ((1, 8, 32, 128, 512, 2048) if "batch" in parts else ()):
             r = time_uniform(B, 100, 100, 0, dt, steps, seed=1200, serial=B <= 128)
             r["batched_solves_per_s"] = round(B / ((r["fwd_ms"] + r["bwd_ms"]) * 1e-3), 1)
             if "serial_ms" in r:
@@ -411,18 +413,33 @@ def bench_sweep(args):
             print("sweep batch %s B=%d: %s" % (dt, B, r), file=sys.stderr, flush=True)
     rows_box = []
     for dt in dts:
-        for n in (60, 100) + ((200,) if dt == "f32" else ()):
+        for n in ((60, 100) + ((200,) if dt == "f32" else ()) if "box" in parts else ()):
             r = time_box(n, dt, steps)
             rows_box.append({"dtype": dt, "batch": 128, "nz": n, "nineq": 2 * n, **r})
             print("sweep box %s nz=%d: %s" % (dt, n, r), file=sys.stderr, flush=True)
+    # the paper's elimination order (Section 3.1.1) against the tiled variant
+    # that forms H, at nz = 100 and nineq from 10 to nz
+    rows_elim = []
+    from paper_1703_00443_amd import binding as qb
+    for dt in dts:
+        for m in ((10, 25, 50, 100) if "elim" in parts else ()):
+            r = {"dtype": dt, "batch": 128, "nz": 100, "nineq": m}
+            for name, v in (("tiled", qb.VARIANT_TILED), ("elim", qb.VARIANT_ELIM)):
+                t = time_uniform(128, 100, m, 0, dt, steps, seed=1300 + m, variant=v)
+                r.update({name + "_" + k: val for k, val in t.items()})
+            r["fwd_speedup"] = round(r["tiled_fwd_ms"] / r["elim_fwd_ms"], 3)
+            rows_elim.append(r)
+            print("sweep elim %s nineq=%d: %s" % (dt, m, r), file=sys.stderr, flush=True)
     return {"metric": "QP layer time vs size and vs batch (paper's solver-timing experiments)",
             "unit": "ms per call", "n_gpus": 1, "steps": steps, "higher_is_better": False,
             "data": "synthetic (seeded generator of the paper's timing experiment, row-normalised G)",
             "config": {"workload": "sizes nz=nineq in {10,50,100,500} at batch 128; batch sizes "
                                    "1..2048 at nz=nineq=100; neq=0; fwd and bwd timed apart; "
                                    "box QPs (G = [I; -I]) at batch 128 with and without "
-                                   "QP_FLAG_G_UNIT_ROWS"},
-            "size_sweep": rows_size, "batch_sweep": rows_batch, "box_qp": rows_box}
+                                   "QP_FLAG_G_UNIT_ROWS; the paper's elimination order against "
+                                   "the tiled variant at nz=100, nineq in {10,25,50,100}"},
+            "size_sweep": rows_size, "batch_sweep": rows_batch, "box_qp": rows_box,
+            "elimination_order": rows_elim}
 
 
 def main():
@@ -440,6 +457,8 @@ def main():
                          "one persistent launch; serving: Poisson request stream, p50/p99 latency; "
                          "sweep: the paper's size and batch-size timing experiments")
     ap.add_argument("--count", type=int, default=0, help="problems/requests for uneven/serving")
+    ap.add_argument("--sweep-parts", default="size,batch,box,elim",
+                    help="sweep: which of its row sets to run (comma-separated)")
     ap.add_argument("--no-buckets", action="store_true",
                     help="uneven: skip the per-bucket launches (counter runs of the full launch)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,

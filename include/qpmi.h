@@ -57,14 +57,17 @@ enum {
     QP_STATUS_OPTIMAL = 0,   /* stopping test met (see qp_opts.tol)                     */
     QP_STATUS_MAX_ITER = 1,  /* max_iter Newton steps taken; last iterate returned      */
     QP_STATUS_BREAKDOWN = 2, /* non-positive or non-finite pivot in the factorization of
-                                the initial point or the first iterate; no factor is
-                                stored and the backward writes zero gradients            */
+                                the initial point or the first iterate (QP_VARIANT_ELIM:
+                                also of Qs); no factor is stored and the backward writes
+                                zero gradients                                           */
     QP_STATUS_NONFINITE = 3, /* non-finite input or iterate; no factor is stored and the
                                 backward writes zero gradients                           */
     QP_STATUS_STALLED = 4    /* the factorization of the next iterate lost positive
                                 definiteness in working precision before the tolerance was
-                                met; the last iterate whose factorization succeeded is
-                                returned (iters counts its steps) with its factor stored  */
+                                met (QP_VARIANT_ELIM: that of H, which the backward reads,
+                                at the iterate the steps ended on); the last iterate whose
+                                factorization succeeded is returned (iters counts its
+                                steps) with its factor stored                            */
 };
 
 typedef struct {
@@ -76,9 +79,12 @@ typedef struct {
 /* Solver options (qp_default_opts fills them per dtype). */
 typedef struct {
     int32_t max_iter;     /* Newton steps after the initial point (default 20)          */
-    int32_t refine_steps; /* backward solve: F64, steps of iterative refinement on the
-                             unreduced K_sym residual (default 1); F32, the FP64 projected
-                             CG preconditioned by the FP32 factor runs at most
+    int32_t refine_steps; /* backward solve: F64, at most this many steps of iterative
+                             refinement on the unreduced K_sym residual, ending once the
+                             error left (estimated from the corrections) is below 1e-8
+                             of the solution or a correction no longer halves
+                             (default 8); F32, the FP64 projected CG
+                             preconditioned by the FP32 factor runs at most
                              10 * refine_steps iterations (default 3, so 30)              */
     double tol;           /* stop when max(mu, |r_x|inf, |r_s|inf, |r_y|inf) <= tol,
                              mu = s^T lambda / nineq (default 1e-8 F64, 1e-3 F32)        */
@@ -104,7 +110,19 @@ enum {
     QP_VARIANT_GENERIC = 1, /* one workgroup per problem, factor in global memory        */
     QP_VARIANT_LDS = 2,     /* one workgroup per problem, factor resident in LDS          */
     QP_VARIANT_TILED = 3,   /* register-resident 16x16 MFMA tiles (nz <= 128; FP32 <= 256) */
-    QP_VARIANT_STREAM = 4   /* factor in the state buffer, 16x16 MFMA tiles streamed       */
+    QP_VARIANT_STREAM = 4,  /* factor in the state buffer, 16x16 MFMA tiles streamed       */
+    QP_VARIANT_ELIM = 5     /* the paper's elimination order (Section 3.1.1, the footnote on
+                               the LU of K_sym): Qs (nz x nz) and the Schur complement on A
+                               (neq x neq) factored once per solve, only an nineq x nineq
+                               matrix C + D(s / lambda), C = G M G^T with M the inverse of
+                               [Qs A^T; A 0] restricted to z, factored per Newton step.
+                               Requires Qs positive definite (otherwise BREAKDOWN),
+                               nz <= 128, nineq <= nz rounded up to a multiple of 16, and
+                               its LDS regions (G U_Q among them) fitting; elsewhere the
+                               automatic plan runs.  Cheaper per step than forming H where
+                               nineq < nz.  The forward ends by factoring H at the returned
+                               iterate, so the state and the backward are those of the
+                               other variants.  Results equal theirs up to rounding.      */
 };
 
 /* Problem data of a uniform batch: device pointers plus per-problem strides in
@@ -253,7 +271,7 @@ int32_t qp_last_hip_error(void);
 /* The factorization policy the forward runs for one problem of `dims` when
  * `variant` (a QP_VARIANT_*, 0 = automatic) is requested, on the current
  * device: *policy receives QP_VARIANT_GENERIC (factor in global memory),
- * QP_VARIANT_LDS, QP_VARIANT_TILED or QP_VARIANT_STREAM, and *lds_bytes (may
+ * QP_VARIANT_LDS, QP_VARIANT_TILED, QP_VARIANT_STREAM or QP_VARIANT_ELIM, and *lds_bytes (may
  * be NULL) the dynamic LDS of its workgroup.  The plan depends on the problem's
  * own dims, the variant and the device's LDS size only.  Host-side; launches
  * nothing.  Returns QP_OK, QP_EDTYPE, QP_EARG or QP_ETOOBIG (no policy fits). */

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libqpmi.so")
 QP_F32, QP_F64 = 0, 1
 QP_OK, QP_EARG, QP_EWS, QP_EDTYPE, QP_EHIP, QP_ENODEV, QP_ETOOBIG = 0, -1, -2, -3, -4, -5, -6
 STATUS_OPTIMAL, STATUS_MAX_ITER, STATUS_BREAKDOWN, STATUS_NONFINITE, STATUS_STALLED = 0, 1, 2, 3, 4
-VARIANT_AUTO, VARIANT_GENERIC, VARIANT_LDS, VARIANT_TILED, VARIANT_STREAM = 0, 1, 2, 3, 4
+VARIANT_AUTO, VARIANT_GENERIC, VARIANT_LDS, VARIANT_TILED, VARIANT_STREAM, VARIANT_ELIM = 0, 1, 2, 3, 4, 5
 FLAG_G_UNIT_ROWS = 1  # qp_opts.flags: every row of G is a signed unit vector
 
 _ERRNAMES = {QP_EARG: "QP_EARG", QP_EWS: "QP_EWS", QP_EDTYPE: "QP_EDTYPE", QP_EHIP: "QP_EHIP",

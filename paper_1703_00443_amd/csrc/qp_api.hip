@@ -76,7 +76,7 @@ int32_t qp_last_hip_error(void) { return g_last_hip_error; }
 
 int32_t qp_plan(qp_dtype dtype, qp_dims d, int32_t variant, int32_t *policy, int32_t *lds_bytes) {
     if (!dtype_ok(dtype)) return QP_EDTYPE;
-    if (!dims_ok(d) || !policy || variant < 0 || variant > QP_VARIANT_STREAM) return QP_EARG;
+    if (!dims_ok(d) || !policy || variant < 0 || variant > QP_VARIANT_ELIM) return QP_EARG;
     int lds = 0;
     const int pol = fwd_plan(esize(dtype), d.nz, d.nineq, d.neq, variant, device_lds_limit(), &lds);
     if (pol == kPolicyNone) return QP_ETOOBIG;
@@ -84,6 +84,7 @@ int32_t qp_plan(qp_dtype dtype, qp_dims d, int32_t variant, int32_t *policy, int
         case kPolicyGenericGlobal: *policy = QP_VARIANT_GENERIC; break;
         case kPolicyGenericLds: *policy = QP_VARIANT_LDS; break;
         case kPolicyStream: *policy = QP_VARIANT_STREAM; break;
+        case kPolicyElim: *policy = QP_VARIANT_ELIM; break;
         default: *policy = QP_VARIANT_TILED; break;
     }
     if (lds_bytes) *lds_bytes = lds;
@@ -95,7 +96,7 @@ int32_t qp_default_opts(qp_dtype dtype, qp_opts *o) {
     if (!dtype_ok(dtype)) return QP_EDTYPE;
     memset(o, 0, sizeof(*o));
     o->max_iter = 20;
-    o->refine_steps = dtype == QP_F64 ? 1 : 3;
+    o->refine_steps = dtype == QP_F64 ? 8 : 3;
     o->tol = dtype == QP_F64 ? 1e-8 : 1e-3;
     o->variant = QP_VARIANT_AUTO;
     o->flags = 0;
@@ -125,7 +126,7 @@ int32_t qp_workspace_query(qp_dtype dtype, int32_t batch, qp_dims d, const qp_op
 static int32_t check_opts(const qp_opts *o) {
     if (!o) return QP_EARG;
     if (o->max_iter < 0 || o->max_iter > 100000 || o->refine_steps < 0 || o->refine_steps > 100 ||
-        !(o->tol >= 0.0) || (o->flags & ~(uint32_t)QP_FLAG_G_UNIT_ROWS) != 0 || o->variant < 0 || o->variant > QP_VARIANT_STREAM)
+        !(o->tol >= 0.0) || (o->flags & ~(uint32_t)QP_FLAG_G_UNIT_ROWS) != 0 || o->variant < 0 || o->variant > QP_VARIANT_ELIM)
         return QP_EARG;
     return QP_OK;
 }
@@ -258,7 +259,7 @@ static bool desc_ok(const qp_problem_desc &d) {
     qp_dims dd = {d.nz, d.nineq, d.neq};
     return dims_ok(dd) && d.Q >= 0 && d.q >= 0 && d.A >= 0 && d.b >= 0 && d.G >= 0 && d.h >= 0 &&
            d.z >= 0 && d.lam >= 0 && d.nu >= 0 && d.state >= 0 && d.variant >= 0 &&
-           d.variant <= QP_VARIANT_STREAM && (d.state % kAlignBytes) == 0;
+           d.variant <= QP_VARIANT_ELIM && (d.state % kAlignBytes) == 0;
 }
 
 int32_t qp_varlen_workspace_query(qp_dtype dtype, int32_t count, const qp_problem_desc *dh,
@@ -298,12 +299,15 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
     const int esz = esize(dtype);
     const int lim = device_lds_limit();
     int lds = 0;
+    bool with_elim = false;
     for (int i = 0; i < count; ++i) {
         const qp_problem_desc &d = desc_host[i];
         if (!desc_ok(d)) return QP_EARG;
         const int var = d.variant ? d.variant : opts->variant;
         int l = 0;
-        if (fwd_plan(esz, d.nz, d.nineq, d.neq, var, lim, &l) == kPolicyNone) return QP_ETOOBIG;
+        const int pol = fwd_plan(esz, d.nz, d.nineq, d.neq, var, lim, &l);
+        if (pol == kPolicyNone) return QP_ETOOBIG;
+        with_elim |= pol == kPolicyElim;
         lds = std::max(lds, l);
     }
     FwdLaunch L;
@@ -322,7 +326,8 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
     L.variant = opts->variant;
     L.flags = opts->flags;
     L.queue = (int *)ws;
-    L.grid = std::min(count, fwd_resident_workgroups(dtype, lds));
+    L.with_elim = with_elim ? 1 : 0;
+    L.grid = std::min(count, fwd_resident_workgroups(dtype, lds, with_elim));
     return hip_ret(launch_forward(dtype, L, (hipStream_t)stream));
 }
 

@@ -331,6 +331,19 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         for (int k = tid; k < m; k += NT) { ds[k] = -tm[k]; dl[k] = D[k] * tm[k]; }
         __syncthreads();
 
+        // Iterative refinement on the unreduced K_sym residual, at most
+        // refine_steps steps.  Each step multiplies the error by a factor rho
+        // that the corrections estimate: for the first one its own size
+        // relative to the solution (the relative error of one reduced solve),
+        // later the ratio of consecutive corrections.  It stops once the error
+        // left, the correction times rho, is below 1e-8 of the solution; a
+        // correction larger than half the previous one (no longer converging)
+        // is not applied.  Near the end of a solve H can be ill-conditioned
+        // enough that one step leaves an adjoint error of 1e-2.  Near the end of a solve H
+        // can be ill-conditioned enough that one step leaves an adjoint error
+        // of 1e-2 where several steps reach 1e-6 or better.
+        T *red = sm + Lo.red;
+        T prev_applied = pinf<T>();
         for (int r = 0; r < L.refine_steps; ++r) {
             // residual of K_sym [dz; ds; dl; dn] = [-g; 0; 0; 0]
             mv_rows<T, NT>(Q, n, n, n, dz, tn);
@@ -360,6 +373,17 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
             kkt_solve<T, NT>(U, u_ld(n), Wt, US, n, p, f, r4, y, tp, tp2, ez, en, scr);
             mv_rows<T, NT>(G, n, m, n, ez, tm);
             __syncthreads();
+            T emax = 0, nx = 0, dmy = 0;  // nx: minus the largest entry of the solution
+            for (int i = tid; i < n; i += NT) { emax = fmax(emax, fabs(ez[i])); nx = fmin(nx, -fabs(dz[i])); }
+            for (int k = tid; k < m; k += NT) {
+                const T e_s = r3[k] - tm[k];
+                const T e_l = r2[k] - D[k] * e_s;
+                emax = fmax(emax, fmax(fabs(e_s), fabs(e_l)));
+                nx = fmin(nx, -fmax(fabs(ds[k]), fabs(dl[k])));
+            }
+            for (int k = tid; k < p; k += NT) { emax = fmax(emax, fabs(en[k])); nx = fmin(nx, -fabs(dn[k])); }
+            block_reduce3<T, NT>(dmy, emax, nx, red);
+            if (r > 0 && emax > T(0.5) * prev_applied) break;
             for (int k = tid; k < m; k += NT) {
                 const T e_s = r3[k] - tm[k];
                 const T e_l = r2[k] - D[k] * e_s;
@@ -369,6 +393,12 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
             for (int i = tid; i < n; i += NT) dz[i] += ez[i];
             for (int k = tid; k < p; k += NT) dn[k] += en[k];
             __syncthreads();
+            {
+                const T xs = fmax(-nx, T(1e-300));
+                const T rho = r == 0 ? emax / xs : emax / prev_applied;
+                if (emax * rho <= T(1e-8) * xs) break;
+            }
+            prev_applied = emax;
         }
         for (int i = tid; i < n; i += NT) P.adj[i] = dz[i];
         for (int k = tid; k < m; k += NT) P.adj[n + k] = dl[k];

@@ -12,11 +12,11 @@ __global__ void qp_zero_counter_kernel(int *c) { *c = 0; }
 
 extern template hipError_t launch_fwd_t<float>(const FwdLaunch &, hipStream_t);
 extern template hipError_t launch_fwd_t<double>(const FwdLaunch &, hipStream_t);
-extern template int resident_t<float>(int);
-extern template int resident_t<double>(int);
+extern template int resident_t<float>(int, bool);
+extern template int resident_t<double>(int, bool);
 
-int fwd_resident_workgroups(qp_dtype dt, int lds_bytes) {
-    return dt == QP_F64 ? resident_t<double>(lds_bytes) : resident_t<float>(lds_bytes);
+int fwd_resident_workgroups(qp_dtype dt, int lds_bytes, bool with_elim) {
+    return dt == QP_F64 ? resident_t<double>(lds_bytes, with_elim) : resident_t<float>(lds_bytes, with_elim);
 }
 
 hipError_t launch_forward(qp_dtype dt, const FwdLaunch &L, hipStream_t st) {

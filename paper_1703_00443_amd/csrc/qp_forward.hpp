@@ -9,6 +9,7 @@
 //
 // Included by one translation unit per element type.
 #pragma once
+#include "qp_elim.hpp"
 #include "qp_stream.hpp"
 
 namespace qpmi {
@@ -18,7 +19,13 @@ constexpr int kFwdThreads = 64 * kTiledWaves;
 __host__ __device__ inline int plan_policy(int esz, int n, int m, int p, int variant, int lds_limit,
                                            int *lds_bytes) {
     const int base = IpmLayout(n, m, p).end;
-    if (variant == QP_VARIANT_AUTO || variant == QP_VARIANT_TILED) {
+    if (variant == QP_VARIANT_ELIM && n <= kTiledMaxN && m <= u_ld(n)) {
+        // taken only on request (it needs Qs positive definite); where it does
+        // not apply the automatic plan runs
+        const int el = elim_lds_elems(base, n, m, p) * esz;
+        if (el <= lds_limit) { *lds_bytes = el; return kPolicyElim; }
+    }
+    if (variant == QP_VARIANT_AUTO || variant == QP_VARIANT_TILED || variant == QP_VARIANT_ELIM) {
         if (n <= kTiledMaxN) {
             const int gl = TiledLayout<true>(base, n, m, p).end * esz;
             if (gl <= lds_limit) { *lds_bytes = gl; return kPolicyTiledGLds; }
@@ -29,7 +36,7 @@ __host__ __device__ inline int plan_policy(int esz, int n, int m, int p, int var
             if (gg <= lds_limit) { *lds_bytes = gg; return kPolicyTiledBig; }
         }
     }
-    if (variant == QP_VARIANT_AUTO || variant == QP_VARIANT_STREAM) {
+    if (variant == QP_VARIANT_AUTO || variant == QP_VARIANT_STREAM || variant == QP_VARIANT_ELIM) {
         int kc = 0;
         bool s_lds = true;
         if (stream_plan(esz, base, n, m, p, lds_limit, &kc, &s_lds)) {
@@ -68,7 +75,10 @@ __device__ __forceinline__ void run_tiled(int pol, const Prob<T> &P, T *sm, cons
     }
 }
 
-template <typename T>
+// ELIM: the instantiation that also carries the elimination-order policy,
+// launched only when some problem of the batch plans it (the policy's code in
+// the kernel costs the others registers).
+template <typename T, bool ELIM>
 __global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunch L) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int next_idx;
@@ -93,6 +103,11 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunc
         } else if (pol == kPolicyStream) {
             if (P.p > 0) run_policy<T, StreamFactor<T, true>>(P, sm, L);
             else run_policy<T, StreamFactor<T, false>>(P, sm, L);
+        } else if (ELIM && pol == kPolicyElim) {
+            if constexpr (ELIM) {
+                if (P.p > 0) run_policy<T, ElimFactor<T, true>>(P, sm, L);
+                else run_policy<T, ElimFactor<T, false>>(P, sm, L);
+            }
         } else if (pol == kPolicyGenericLds) {
             run_policy<T, GenericFactor<T, kFwdThreads, true>>(P, sm, L);
         } else {
@@ -116,11 +131,12 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_uniform_kernel(FwdLaun
     }
 }
 
-template <class K>
-static void set_lds_limit_once(K kern, int lds_limit) {
+// Once per kernel (the flag is per instantiation, i.e. per kernel function).
+template <auto Kern>
+static void set_lds_limit_once(int lds_limit) {
     static bool done = false;
     if (!done) {
-        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
+        (void)hipFuncSetAttribute((const void *)Kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit);
         done = true;
     }
 }
@@ -128,7 +144,7 @@ static void set_lds_limit_once(K kern, int lds_limit) {
 template <typename T, class F>
 static hipError_t launch_uniform(const FwdLaunch &L, hipStream_t st) {
     auto kern = qp_forward_uniform_kernel<T, F>;
-    set_lds_limit_once(kern, L.lds_limit);
+    set_lds_limit_once<qp_forward_uniform_kernel<T, F>>(L.lds_limit);
     hipLaunchKernelGGL(kern, dim3(L.count), dim3(kFwdThreads), L.lds_bytes, st, L);
     return hipGetLastError();
 }
@@ -163,11 +179,15 @@ hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
         if (pol == kPolicyStream)
             return L.neq > 0 ? launch_uniform<T, StreamFactor<T, true>>(L, st)
                              : launch_uniform<T, StreamFactor<T, false>>(L, st);
+        if (pol == kPolicyElim)
+            return L.neq > 0 ? launch_uniform<T, ElimFactor<T, true>>(L, st)
+                             : launch_uniform<T, ElimFactor<T, false>>(L, st);
         if (pol == kPolicyGenericLds) return launch_uniform<T, GenericFactor<T, kFwdThreads, true>>(L, st);
         return launch_uniform<T, GenericFactor<T, kFwdThreads, false>>(L, st);
     }
-    auto kern = qp_forward_varlen_kernel<T>;
-    set_lds_limit_once(kern, L.lds_limit);
+    auto kern = L.with_elim ? qp_forward_varlen_kernel<T, true> : qp_forward_varlen_kernel<T, false>;
+    if (L.with_elim) set_lds_limit_once<qp_forward_varlen_kernel<T, true>>(L.lds_limit);
+    else set_lds_limit_once<qp_forward_varlen_kernel<T, false>>(L.lds_limit);
     if (L.queue) {
         hipLaunchKernelGGL(qp_zero_counter_kernel, dim3(1), dim3(1), 0, st, L.queue);
         const hipError_t e = hipGetLastError();
@@ -179,13 +199,16 @@ hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
 }
 
 template <typename T>
-int resident_t(int lds_bytes) {
+int resident_t(int lds_bytes, bool with_elim) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T>, kFwdThreads,
-                                                     (size_t)lds_bytes) != hipSuccess || per < 1)
-        per = 1;
+    const hipError_t e =
+        with_elim ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T, true>,
+                                                                 kFwdThreads, (size_t)lds_bytes)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T, false>,
+                                                                 kFwdThreads, (size_t)lds_bytes);
+    if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
 }
 

@@ -3,5 +3,5 @@
 
 namespace qpmi {
 template hipError_t launch_fwd_t<float>(const FwdLaunch &, hipStream_t);
-template int resident_t<float>(int);
+template int resident_t<float>(int, bool);
 }  // namespace qpmi

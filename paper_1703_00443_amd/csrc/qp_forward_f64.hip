@@ -3,5 +3,5 @@
 
 namespace qpmi {
 template hipError_t launch_fwd_t<double>(const FwdLaunch &, hipStream_t);
-template int resident_t<double>(int);
+template int resident_t<double>(int, bool);
 }  // namespace qpmi

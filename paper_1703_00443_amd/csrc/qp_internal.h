@@ -66,6 +66,7 @@ struct FwdLaunch {
     unsigned flags;                        // QP_FLAG_* of the call
     int *queue;                            // varlen: work counter (zeroed by the launch), else null
     int grid;                              // workgroups launched (0 = one per problem)
+    int with_elim;                         // varlen: some problem runs the elimination order
 };
 
 struct BwdLaunch {
@@ -98,11 +99,11 @@ struct BwdLaunch {
 // requested variant and the device LDS limit, so a problem is solved with the
 // same arithmetic alone or inside any batch.
 enum { kPolicyGenericGlobal = 0, kPolicyGenericLds = 1, kPolicyTiledGGlobal = 2, kPolicyTiledGLds = 3,
-       kPolicyTiledBig = 4, kPolicyStream = 5, kPolicyNone = -1 };
+       kPolicyTiledBig = 4, kPolicyStream = 5, kPolicyElim = 6, kPolicyNone = -1 };
 int fwd_plan(int esz, int n, int m, int p, int variant, int lds_limit, int *lds_bytes);
 
 // Workgroups of the forward kernel that fit on the device at once with this LDS.
-int fwd_resident_workgroups(qp_dtype dt, int lds_bytes);
+int fwd_resident_workgroups(qp_dtype dt, int lds_bytes, bool with_elim);
 
 // Dynamic LDS bytes a problem needs in the backward kernel on a device with
 // `lds_limit` bytes per workgroup (FP32 stages Q, G and A there when they fit).

@@ -17,7 +17,11 @@
 //   void solve(f, r4, dz, dnu)                 [H A^T; A 0][dz; dnu] = [f; r4]
 //   void gt_mv(v, out)   out = G^T v           void g_mv(x, out)   out = G x
 //   void qs_mv(z, out)   out = Qs z
-//   void finish()                              write the factor to the state
+//   static constexpr bool kRefineAlways        refine every combined direction
+//   static constexpr bool kSolveGz             solve_g(f, r4, dz, dnu, gz) also
+//                                              returns G dz (see solve_gz)
+//   bool finish(D)                             write the factor of [H A^T; A 0]
+//                                              at D to the state (false: none)
 #pragma once
 #include "qp_core.hpp"
 
@@ -98,6 +102,20 @@ struct IpmLayout {
     }
 };
 
+// dz (and dnu) of the reduced system, and in gz the product G dz that
+// recovers ds = r_s - G dz and dlam = c + D G dz.  A policy whose solve yields
+// w = D G dz itself (F::kSolveGz) returns gz = D^{-1} w: dlam then carries w's
+// own rounding instead of dz's multiplied by D.
+template <typename T, class F>
+__device__ __forceinline__ void solve_gz(F &fac, const T *f, const T *r4, T *dz, T *dnu, T *gz) {
+    if constexpr (F::kSolveGz) {
+        fac.solve_g(f, r4, dz, dnu, gz);
+    } else {
+        fac.solve(f, r4, dz, dnu);
+        fac.g_mv(dz, gz);
+    }
+}
+
 template <typename T, int NT, class F>
 __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayout &Lo, F &fac, int max_iter, T tol,
                           int32_t *status, int32_t *iters) {
@@ -176,9 +194,8 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         for (int i = tid; i < n; i += NT) f[i] -= Pq[i];
         for (int k = tid; k < p; k += NT) tp2[k] = Pb[k];
         __syncthreads();
-        fac.solve(f, tp2, z, nu);
         if (m > 0) {
-            fac.g_mv(z, tm);
+            solve_gz<T>(fac, f, tp2, z, nu, tm);
             T mns = pinf<T>(), mnl = pinf<T>(), dummy = 0;
             for (int k = tid; k < m; k += NT) {
                 const T sk = Ph[k] - tm[k];
@@ -197,6 +214,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             }
             __syncthreads();
         } else {
+            fac.solve(f, tp2, z, nu);
             st = QP_STATUS_OPTIMAL;
             goto store_factor;
         }
@@ -272,8 +290,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         fac.gt_mv(tm, f);
         for (int i = tid; i < n; i += NT) f[i] += rx[i];
         __syncthreads();
-        fac.solve(f, ry, dza, dna);
-        fac.g_mv(dza, tm);
+        solve_gz<T>(fac, f, ry, dza, dna, tm);
         T amin = pinf<T>(), d0 = 0, d1 = 0;
         for (int k = tid; k < m; k += NT) {
             const T ds = rz[k] - tm[k];
@@ -299,8 +316,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         fac.gt_mv(w, f);
         for (int i = tid; i < n; i += NT) f[i] = -f[i];
         __syncthreads();
-        fac.solve(f, tp, dzc, dnc);
-        fac.g_mv(dzc, tm);
+        solve_gz<T>(fac, f, tp, dzc, dnc, tm);
         // combined direction (dz in dza, dnu in dna, ds in tm, dlam in w)
         amin = pinf<T>(); d0 = 0;
         T dzmax = 0;
@@ -330,7 +346,9 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         // overestimated the error seen in the dual residual by about 10x, hence
         // the test against 2.5 tol.  Without it the dual residual can grow from
         // one iterate to the next there instead of shrinking with the step.
-        if (kEps * dzmax * emax * gnorm >= T(2.5) * tol) {
+        // Policies whose solve leaves an error that does not scale with |dz|
+        // (F::kRefineAlways) refine every step.
+        if (F::kRefineAlways || kEps * dzmax * emax * gnorm >= T(2.5) * tol) {
             // e2 = (sigma mu - s lam - dsa dla) - (lam ds + s dl)        -> dla
             for (int k = tid; k < m; k += NT)
                 dla[k] = (sigma * mu - s[k] * lam[k] - dsa[k] * dla[k]) - (lam[k] * dsc[k] + s[k] * dlc[k]);
@@ -360,8 +378,7 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
             fac.gt_mv(dla, tn);    // G^T c
             for (int i = tid; i < n; i += NT) f[i] -= tn[i];
             __syncthreads();
-            fac.solve(f, tp2, dzc, dnc);
-            fac.g_mv(dzc, rz);     // G ddz (r_s is not read again in this step)
+            solve_gz<T>(fac, f, tp2, dzc, dnc, rz);  // G ddz (r_s is not read again in this step)
             amin = pinf<T>(); d0 = 0; d1 = 0;
             for (int k = tid; k < m; k += NT) {
                 const T ds = dsc[k] + (dsa[k] - rz[k]);          // + e3 - G ddz
@@ -383,7 +400,28 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     }
 
 store_factor:
-    fac.finish(D);
+    if (!fac.finish(D)) {
+        // Only a policy whose Newton steps factor another matrix than H (the
+        // elimination order) can get here: H itself lost positive
+        // definiteness at the returned iterate.  As when the next iterate's
+        // factorization fails inside the loop, the previous iterate (kept in
+        // the output buffers since its step) is returned with its factor.
+        if (it >= 1 && (st == QP_STATUS_OPTIMAL || st == QP_STATUS_MAX_ITER)) {
+            for (int i = tid; i < n; i += NT) z[i] = zp[i];
+            for (int k = tid; k < m; k += NT) {
+                s[k] = sp[k];
+                lam[k] = lp[k];
+                D[k] = lp[k] / sp[k];
+            }
+            for (int k = tid; k < p; k += NT) nu[k] = nup[k];
+            __syncthreads();
+            st = QP_STATUS_STALLED;
+            it -= 1;
+            if (!fac.finish(D)) st = QP_STATUS_BREAKDOWN;
+        } else {
+            st = QP_STATUS_BREAKDOWN;
+        }
+    }
 
 finish:
     for (int i = tid; i < n; i += NT) Pz[i] = z[i];

@@ -76,6 +76,8 @@ struct TiledLayout {
 // ---------------------------------------------------------------------------
 template <typename T, int NT, bool HL>
 struct GenericFactor {
+    static constexpr bool kRefineAlways = false;
+    static constexpr bool kSolveGz = false;
     int n, m, p;
     const T *Q, *G, *A;
     T *H;
@@ -121,7 +123,7 @@ struct GenericFactor {
         for (int i = threadIdx.x; i < n; i += NT) out[i] = T(0.5) * (out[i] + tq[i]);
         __syncthreads();
     }
-    __device__ __forceinline__ void finish(const T *D) {
+    __device__ __forceinline__ bool finish(const T *D) {
         if (HL)
             for (int e = threadIdx.x; e < n * n; e += NT) {
                 const int i = e / n, j = e - i * n;
@@ -129,6 +131,7 @@ struct GenericFactor {
             }
         for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
         __syncthreads();
+        return true;
     }
 };
 
@@ -277,6 +280,8 @@ struct TileMap {
 template <typename T, bool GL, int NTL, bool EQ, bool UNIT = false>
 struct TiledFactor {
     static constexpr int NT = 64 * kTiledWaves;
+    static constexpr bool kRefineAlways = false;
+    static constexpr bool kSolveGz = false;
     static constexpr int NS = TileMap<NTL>::NS;
     using v4 = typename Mfma<T>::v4;
     int n, m, p, nt, np, pt, ldg, lds, ldu;
@@ -452,6 +457,30 @@ struct TiledFactor {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 if (Mfma<T>::row(g, r) < c) sq[s][r] = T(0);  // X part of the diagonal tile
+        }
+    }
+
+    // The register tiles from a symmetric n x n matrix whose strict lower
+    // triangle is that of C (row-major, ld ldc) and whose diagonal is diag: the
+    // same tiles form() leaves, with no contraction (identity on the padding,
+    // the X part of the diagonal tiles zero).
+    __device__ __forceinline__ void seed(const T *C, int ldc, const T *diag) {
+        lane_ids();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int I = trow(s), J = tcol(s);
+            v4 acc = {0, 0, 0, 0};
+            if (I < nt && J < nt && I >= J) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * I + Mfma<T>::row(g, r), col = 16 * J + c;
+                    const bool in = row < n && col < n, lo = in && col < row;
+                    const T v = C[lo ? (size_t)row * ldc + col : 0];
+                    const T d = diag[in && row == col ? row : 0];
+                    acc[r] = lo ? v : (in && row == col ? d : (!in && row == col ? T(1) : T(0)));
+                }
+            }
+            sq[s] = acc;
         }
     }
 
@@ -778,7 +807,7 @@ struct TiledFactor {
         for (int i = threadIdx.x; i < n; i += NT) out[i] = T(0.5) * (out[i] + xv[i]);
         __syncthreads();
     }
-    __device__ __forceinline__ void finish(const T *D) {
+    __device__ __forceinline__ bool finish(const T *D) {
         store_u();
         for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
         if constexpr (EQ)
@@ -787,6 +816,7 @@ struct TiledFactor {
                 US[e] = S[i * lds + j];
             }
         __syncthreads();
+        return true;
     }
 };
 

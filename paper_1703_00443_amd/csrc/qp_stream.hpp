@@ -58,6 +58,8 @@ __host__ __device__ inline bool stream_plan(int esz, int base, int n, int m, int
 
 template <typename T, bool EQ>
 struct StreamFactor {
+    static constexpr bool kRefineAlways = false;
+    static constexpr bool kSolveGz = false;
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr int GT = 8;   // form(): tiles per wavefront and pass
     static constexpr int SE = sizeof(T) == 4 ? 32 : 16;  // form(): G elements staged per thread and chunk
@@ -402,7 +404,7 @@ struct StreamFactor {
         for (int i = threadIdx.x; i < n; i += NT) out[i] = T(0.5) * (out[i] + xv[i]);
         __syncthreads();
     }
-    __device__ __forceinline__ void finish(const T *D) {
+    __device__ __forceinline__ bool finish(const T *D) {
         for (int k = threadIdx.x; k < m; k += NT) Dst[k] = D[k];
         if constexpr (EQ)
             if (s_lds)
@@ -411,6 +413,7 @@ struct StreamFactor {
                     US[e] = S[i * lds + j];
                 }
         __syncthreads();
+        return true;
     }
 };
 

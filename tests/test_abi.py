@@ -68,7 +68,7 @@ def test_defaults_and_sizes():
     binding, lib = _lib()
     o = binding.qp_opts()
     assert lib.qp_default_opts(binding.QP_F64, ctypes.byref(o)) == 0
-    assert (o.max_iter, o.refine_steps, o.tol) == (20, 1, 1e-8)
+    assert (o.max_iter, o.refine_steps, o.tol) == (20, 8, 1e-8)
     assert lib.qp_default_opts(binding.QP_F32, ctypes.byref(o)) == 0
     assert (o.max_iter, o.refine_steps, o.tol) == (20, 3, 1e-3)
     assert lib.qp_default_opts(7, ctypes.byref(o)) == binding.QP_EDTYPE

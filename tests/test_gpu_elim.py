@@ -1,0 +1,137 @@
+"""The paper's elimination order (QP_VARIANT_ELIM; Section 3.1.1, the footnote
+on the LU of K_sym) on the GPU against the FP64 oracle: z, s, lambda, nu and
+every gradient of every problem, at nineq < nz, nineq = nz, with and without
+equality rows, with no inequality rows, and with ragged sizes that end in a
+partial 16x16 tile.  The variant factors Qs once per solve, so a Q that is not
+positive definite must end BREAKDOWN with zero gradients."""
+import numpy as np
+import pytest
+
+from paper_1703_00443_amd import synth
+
+from parity import compare_problem
+
+pytestmark = pytest.mark.gpu
+
+ELIM = 5
+
+
+def _run(batch, dtype, variant=ELIM, need_grad=True):
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(dtype))).to(dev)
+    n, m, p = batch.dims
+    prob = qb.make_problem(T(batch.Q), T(batch.q), T(batch.A) if p else None,
+                           T(batch.b) if p else None, T(batch.G) if m else None,
+                           T(batch.h) if m else None)
+    opts = qb.default_opts(tdt, variant=variant)
+    fw = qb.forward(prob, opts)
+    gr = qb.backward(prob, fw, T(batch.g), opts) if need_grad else None
+    torch.cuda.synchronize()
+    out = {k: getattr(fw, k).cpu().numpy() for k in ("z", "lam", "nu", "s", "status", "iters")}
+    if gr is not None:
+        for k in ("dQ", "dq", "dA", "db", "dG", "dh"):
+            v = getattr(gr, k)
+            out[k] = None if v is None else v.cpu().numpy()
+    return out
+
+
+def _check_all(batch, out, dtype, tag):
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    B = batch.Q.shape[0]
+    for i in range(B):
+        assert int(out["status"][i]) in (0, 1, 4), "%s problem %d status %d" % (tag, i, out["status"][i])
+
+    def one(i):
+        got = {k: (out[k][i] if out.get(k) is not None else None)
+               for k in ("z", "lam", "nu", "s", "iters", "dQ", "dq", "dA", "db", "dG", "dh")}
+        return compare_problem(batch.problem(i), got, dtype, tag="%s[%d]" % (tag, i), grads=True)
+
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1, B))) as ex:
+        list(ex.map(one, range(B)))
+
+
+# nineq < nz (where the variant pays), nineq = 0, ragged tails; FP64 also at
+# nineq >= nz.  In FP32 the nineq x nineq matrix G Qs^{-1} G^T + D^{-1} is too
+# ill-conditioned at nineq >= nz for this generator (Qs has eigenvalues down to
+# 1e-3): some problems do not reach the tolerance there.
+SHAPES = [(100, 25, 0), (100, 50, 0), (64, 16, 8), (37, 13, 5), (20, 0, 4), (9, 3, 0), (128, 40, 12)]
+CASES = [(np.float64, d) for d in SHAPES + [(100, 100, 0), (50, 60, 0)]] + [(np.float32, d) for d in SHAPES]
+
+
+@pytest.mark.parametrize("dtype,dims", CASES)
+def test_elimination_order_parity(dtype, dims):
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    n, m, p = dims
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    assert qb.plan(tdt, n, m, p, ELIM)[0] == ELIM, "the variant does not apply at %s" % (dims,)
+    b = synth.make_batch(seed=5150 + n + 7 * m + 31 * p, B=12, n=n, m=m, p=p)
+    out = _run(b, dtype)
+    _check_all(b, out, dtype, "elim%s_%s" % (dims, np.dtype(dtype).name))
+
+
+def test_elimination_order_paper_scale_every_problem():
+    """The paper-scale batch (128 problems, nz = nineq = 100, FP64) through the
+    elimination order: every problem against the oracle."""
+    dtype = np.float64
+    b = synth.make_batch(**synth.PAPER_SCALE)
+    out = _run(b, dtype)
+    assert np.all(out["status"] == 0), np.bincount(out["status"])
+    _check_all(b, out, dtype, "elim_paper_scale_%s" % np.dtype(dtype).name)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_elimination_order_needs_positive_definite_q(dtype):
+    """Q = 0 in one problem: Qs cannot be factored, so that problem ends
+    BREAKDOWN with zero gradients; the other problems of the batch are
+    unaffected."""
+    assert __import__("paper_1703_00443_amd.binding", fromlist=["plan"]).plan(
+        __import__("torch").float64, 40, 20, 0, ELIM)[0] == ELIM
+    b = synth.make_batch(seed=77, B=4, n=40, m=20, p=0)
+    b.Q[1] = 0.0
+    out = _run(b, dtype)
+    assert int(out["status"][1]) == 2
+    for k in ("dQ", "dq", "dG", "dh"):
+        assert np.all(out[k][1] == 0), k
+    assert all(int(out["status"][i]) == 0 for i in (0, 2, 3))
+
+
+def test_elimination_order_plan_falls_back():
+    """Where the variant does not apply (nz above 128, or nineq above nz
+    rounded up to 16) the automatic plan runs."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    for dt in (torch.float64, torch.float32):
+        assert qb.plan(dt, 100, 30, 0, ELIM)[0] == ELIM
+        assert qb.plan(dt, 200, 30, 0, ELIM)[0] == qb.plan(dt, 200, 30, 0, 0)[0]
+        assert qb.plan(dt, 100, 200, 0, ELIM)[0] == qb.plan(dt, 100, 200, 0, 0)[0]
+        assert qb.plan(dt, 100, 112, 0, ELIM)[0] == ELIM
+        assert qb.plan(dt, 100, 113, 0, ELIM)[0] == qb.plan(dt, 100, 113, 0, 0)[0]
+
+
+def test_elimination_order_in_uneven_batch():
+    """Problems that request the elimination order inside an uneven batch, next
+    to problems on the automatic plan: each result bitwise equal to the same
+    problem solved alone, and z of every problem against the oracle."""
+    import torch
+    from paper_1703_00443_amd.varlen import VarlenBatch
+    from parity import TOL_Z, oracle_replay, z_err
+    dims = [(100, 30, 0), (40, 80, 0), (64, 20, 6), (17, 5, 0), (120, 60, 10), (8, 16, 2)]
+    probs = synth.make_varlen(91, dims, dtype=np.float32)
+    variants = [ELIM, 0, ELIM, ELIM, ELIM, 0]
+    vb = VarlenBatch(probs, dtype=torch.float32, variants=variants)
+    vb.forward()
+    torch.cuda.synchronize()
+    for i, P in enumerate(probs):
+        one = VarlenBatch([P], dtype=torch.float32, variants=[variants[i]])
+        one.forward()
+        torch.cuda.synchronize()
+        a, r = one.result(0), vb.result(i)
+        np.testing.assert_array_equal(a["z"], r["z"])
+        assert int(r["status"]) in (0, 1, 4)
+        ref = oracle_replay(P, int(r["iters"]), np.float32)
+        assert z_err(r["z"], ref["z"]) <= TOL_Z[np.float32]
