@@ -6,7 +6,7 @@ import os
 import numpy as np
 
 from paper_1703_00443_amd import synth
-from paper_1703_00443_amd.autotune import BUCKETS, AutotuneTable, bucket_of, candidates
+from paper_1703_00443_amd.autotune import BUCKETS, AutotuneTable, bucket_of, candidates, ratio_of
 
 
 def test_problem_regenerates_alone():
@@ -58,6 +58,16 @@ def test_autotune_buckets_and_lookup(tmp_path):
     assert 3 in candidates(128, "f64") and 3 not in candidates(129, "f64")
     assert 3 in candidates(256, "f32") and 3 not in candidates(257, "f32")
     assert 4 in candidates(1000, "f64")
+    # the elimination order: nz <= 128 and nineq <= nz rounded up to 16
+    assert 5 in candidates(100, "f64", 25) and 5 in candidates(100, "f32", 112)
+    assert 5 not in candidates(100, "f64", 113) and 5 not in candidates(129, "f32", 10)
+    assert 5 not in candidates(100, "f64")               # nineq not given
+    # ratio classes: an entry of the class wins, else the class-less entry
+    assert [ratio_of(100, m) for m in (25, 26, 50, 51, 100, 101)] == ["r0", "r1", "r1", "r2", "r2", "r3"]
+    t = AutotuneTable({"f64": {"noeq": {"4": 3}, "noeq/r0": {"4": 5}}})
+    assert t.variant_for("f64", 100, 20, 0) == 5
+    assert t.variant_for("f64", 100, 60, 0) == 3
+    assert t.variant_for("f64", 100, 20, 3) == 0
 
 
 def test_committed_table_is_valid():
