@@ -346,9 +346,14 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         // overestimated the error seen in the dual residual by about 10x, hence
         // the test against 2.5 tol.  Without it the dual residual can grow from
         // one iterate to the next there instead of shrinking with the step.
+        // Early steps, whose residuals are far above that error, skip it: it
+        // runs only when the bound is also at least a tenth of the current
+        // error max(mu, residuals) (the error itself then at least about 1% of
+        // it), which is where the next residual can be made of it.
         // Policies whose solve leaves an error that does not scale with |dz|
         // (F::kRefineAlways) refine every step.
-        if (F::kRefineAlways || kEps * dzmax * emax * gnorm >= T(2.5) * tol) {
+        const T rbound = kEps * dzmax * emax * gnorm;
+        if (F::kRefineAlways || (rbound >= T(2.5) * tol && rbound >= T(0.1) * err)) {
             // e2 = (sigma mu - s lam - dsa dla) - (lam ds + s dl)        -> dla
             for (int k = tid; k < m; k += NT)
                 dla[k] = (sigma * mu - s[k] * lam[k] - dsa[k] * dla[k]) - (lam[k] * dsc[k] + s[k] * dlc[k]);
