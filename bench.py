@@ -457,6 +457,8 @@ def main():
                          "one persistent launch; serving: Poisson request stream, p50/p99 latency; "
                          "sweep: the paper's size and batch-size timing experiments")
     ap.add_argument("--count", type=int, default=0, help="problems/requests for uneven/serving")
+    ap.add_argument("--bwd-fp32", action="store_true",
+                    help="paper workload, FP32: the backward in FP32 only (QP_FLAG_BWD_FP32)")
     ap.add_argument("--sweep-parts", default="size,batch,box,elim",
                     help="sweep: which of its row sets to run (comma-separated)")
     ap.add_argument("--no-buckets", action="store_true",
@@ -499,7 +501,7 @@ def main():
     T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(npdt))).to(dev)
     prob = qb.make_problem(T(bnp.Q), T(bnp.q), None, None, T(bnp.G), T(bnp.h))
     g = T(bnp.g)
-    opts = qb.default_opts(tdt)
+    opts = qb.default_opts(tdt, flags=qb.FLAG_BWD_FP32 if args.bwd_fp32 else 0)
     fw = qb.forward(prob, opts)
     _, bws = qb.workspace_bytes(tdt, B, n, m, p, opts)
     ws = torch.empty(bws, dtype=torch.uint8, device=dev)
@@ -564,7 +566,9 @@ def main():
         "config": {"workload": "paper-scale batch: 128 QPs, nz=100, nineq=100, neq=0, "
                                "row-normalised G, fwd+bwd",
                    "batch": B, "nz": n, "nineq": m, "neq": p,
-                   "tol": opts.tol, "max_iter": opts.max_iter, "refine_steps": opts.refine_steps},
+                   "tol": opts.tol, "max_iter": opts.max_iter, "refine_steps": opts.refine_steps,
+                   "backward": ("FP32 refinement (QP_FLAG_BWD_FP32)" if args.bwd_fp32 and args.dtype == "f32"
+                                else "FP64 projected CG" if args.dtype == "f32" else "FP64 refinement")},
         "roofline": {"kernel": "qp_forward_uniform_kernel", "bound": "mfma", "achieved": round(achieved, 4),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
                      "traffic": traffic,

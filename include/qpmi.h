@@ -103,7 +103,15 @@ typedef struct {
  *   dense path's up to rounding.  Used by qp_forward_batched for problems the
  *   register-tile policy takes; elsewhere, and in qp_forward_varlen, the flag is
  *   accepted and the dense path runs.  The backward is unchanged. */
-enum { QP_FLAG_G_UNIT_ROWS = 1u };
+/* QP_FLAG_BWD_FP32: the FP32 backward computes in FP32 only: the reduced
+ *   solve with the stored FP32 factor and iterative refinement on the
+ *   unreduced K_sym residual in FP32 (at most refine_steps steps, ending once
+ *   the error left, estimated from the corrections, is below 1e-4 of the
+ *   solution or a correction no longer halves).  Without the flag the FP32
+ *   backward runs a projected conjugate gradient in FP64 preconditioned by the
+ *   FP32 factor, which stays accurate at the ill-conditioned iterates that end
+ *   FP32 solves.  Ignored for FP64. */
+enum { QP_FLAG_G_UNIT_ROWS = 1u, QP_FLAG_BWD_FP32 = 2u };
 
 enum {
     QP_VARIANT_AUTO = 0,
@@ -174,10 +182,11 @@ int32_t qp_forward_batched(qp_dtype dtype, int32_t batch, qp_dims dims, const qp
 
 /* Gradients of a loss l through the QP solution (Section 3.1.1): solve
  * eq. grads-system with the stored factor (no new factorization).  F64: the
- * factor's solve plus opts->refine_steps steps of iterative refinement on the
- * unreduced symmetrised KKT residual.  F32: projected preconditioned conjugate
- * gradients on the reduced system with FP64 vectors and products, the FP32
- * factor as preconditioner (accurate where cond(H) eps32 exceeds 1).  Then
+ * factor's solve plus at most opts->refine_steps steps of iterative refinement
+ * on the unreduced symmetrised KKT residual (see qp_opts.refine_steps).  F32:
+ * projected preconditioned conjugate gradients on the reduced system with FP64
+ * vectors and products, the FP32 factor as preconditioner (accurate where
+ * cond(H) eps32 exceeds 1); with QP_FLAG_BWD_FP32, the F64 scheme in FP32.  Then
  * eq. grads:
  *   dQ = 1/2 (d_z z^T + z d_z^T), dq = d_z, dA = d_nu z^T + nu d_z^T,
  *   db = -d_nu, dG = D(lam) d_lam z^T + lam d_z^T, dh = -D(lam) d_lam.

@@ -25,6 +25,7 @@ QP_OK, QP_EARG, QP_EWS, QP_EDTYPE, QP_EHIP, QP_ENODEV, QP_ETOOBIG = 0, -1, -2, -
 STATUS_OPTIMAL, STATUS_MAX_ITER, STATUS_BREAKDOWN, STATUS_NONFINITE, STATUS_STALLED = 0, 1, 2, 3, 4
 VARIANT_AUTO, VARIANT_GENERIC, VARIANT_LDS, VARIANT_TILED, VARIANT_STREAM, VARIANT_ELIM = 0, 1, 2, 3, 4, 5
 FLAG_G_UNIT_ROWS = 1  # qp_opts.flags: every row of G is a signed unit vector
+FLAG_BWD_FP32 = 2     # qp_opts.flags: the FP32 backward computes in FP32 only
 
 _ERRNAMES = {QP_EARG: "QP_EARG", QP_EWS: "QP_EWS", QP_EDTYPE: "QP_EDTYPE", QP_EHIP: "QP_EHIP",
              QP_ENODEV: "QP_ENODEV", QP_ETOOBIG: "QP_ETOOBIG"}

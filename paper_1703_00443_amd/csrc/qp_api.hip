@@ -126,7 +126,7 @@ int32_t qp_workspace_query(qp_dtype dtype, int32_t batch, qp_dims d, const qp_op
 static int32_t check_opts(const qp_opts *o) {
     if (!o) return QP_EARG;
     if (o->max_iter < 0 || o->max_iter > 100000 || o->refine_steps < 0 || o->refine_steps > 100 ||
-        !(o->tol >= 0.0) || (o->flags & ~(uint32_t)QP_FLAG_G_UNIT_ROWS) != 0 || o->variant < 0 || o->variant > QP_VARIANT_ELIM)
+        !(o->tol >= 0.0) || (o->flags & ~(uint32_t)(QP_FLAG_G_UNIT_ROWS | QP_FLAG_BWD_FP32)) != 0 || o->variant < 0 || o->variant > QP_VARIANT_ELIM)
         return QP_EARG;
     return QP_OK;
 }
@@ -212,7 +212,7 @@ int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_d
     if (ws_bytes < need || (need > 0 && !ws)) return QP_EWS;
     const int esz = esize(dtype);
     const int lim = device_lds_limit();
-    if (bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim) > (size_t)lim) return QP_ETOOBIG;
+    if (bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim, opts->flags) > (size_t)lim) return QP_ETOOBIG;
 
     BwdLaunch L;
     memset(&L, 0, sizeof(L));
@@ -228,7 +228,8 @@ int32_t qp_backward_batched(qp_dtype dtype, int32_t batch, qp_dims d, const qp_d
     L.adj = ws;
     L.adj_stride = adj_stride_elems(d.nz, d.nineq, d.neq);
     L.refine_steps = opts->refine_steps;
-    L.lds_bytes = (int)bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim);
+    L.flags = opts->flags;
+    L.lds_bytes = (int)bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim, opts->flags);
     L.lds_limit = lim;
     L.max_rows = d.nz + d.nineq + d.neq + 1;
     return hip_ret(launch_backward(dtype, L, (hipStream_t)stream));
@@ -355,7 +356,7 @@ int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc 
     std::vector<std::pair<int64_t, int64_t>> adj(count);
     for (int i = 0; i < count; ++i) {
         const qp_problem_desc &d = desc_host[i];
-        const size_t b = bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim);
+        const size_t b = bwd_vec_lds_bytes(esz, d.nz, d.nineq, d.neq, lim, opts->flags);
         if (b > (size_t)lim) return QP_ETOOBIG;
         lds = std::max(lds, (int)b);
         rows = std::max(rows, d.nz + d.nineq + d.neq + 1);
@@ -378,6 +379,7 @@ int32_t qp_backward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc 
     L.adj = ws;
     L.adj_stride = 0;  // varlen: problem j's adjoint at desc.z + desc.lam + desc.nu
     L.refine_steps = opts->refine_steps;
+    L.flags = opts->flags;
     L.lds_bytes = lds;
     L.lds_limit = lim;
     L.max_rows = rows;

@@ -141,15 +141,17 @@ __host__ __device__ inline int bwd_mixed_stage(int n, int m, int p, int lds_limi
     return BwdMixedLayout(n, m, p, 1).end <= lds_limit ? 1 : 0;
 }
 
-// FP64: G (read six times per refinement step) is copied to LDS after the
-// vectors when it fits; the choice depends on dims and the device LDS only.
-__host__ __device__ inline bool bwd_stage_g64(int n, int m, int p, int lds_limit) {
-    return ((size_t)BwdLayout(n, m, p).end + (size_t)m * n) * 8 <= (size_t)lds_limit;
+// Refinement in the working precision (FP64, or FP32 with QP_FLAG_BWD_FP32):
+// G (read six times per refinement step) is copied to LDS after the vectors
+// when it fits; the choice depends on dims, element size and the device LDS only.
+__host__ __device__ inline bool bwd_stage_g(int esz, int n, int m, int p, int lds_limit) {
+    return ((size_t)BwdLayout(n, m, p).end + (size_t)m * n) * esz <= (size_t)lds_limit;
 }
 
-size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit) {
-    if (esz == 4) return (size_t)BwdMixedLayout(n, m, p, bwd_mixed_stage(n, m, p, lds_limit)).end;
-    return ((size_t)BwdLayout(n, m, p).end + (bwd_stage_g64(n, m, p, lds_limit) ? (size_t)m * n : 0)) * esz;
+size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit, unsigned flags) {
+    if (esz == 4 && !(flags & QP_FLAG_BWD_FP32))
+        return (size_t)BwdMixedLayout(n, m, p, bwd_mixed_stage(n, m, p, lds_limit)).end;
+    return ((size_t)BwdLayout(n, m, p).end + (bwd_stage_g(esz, n, m, p, lds_limit) ? (size_t)m * n : 0)) * esz;
 }
 
 template <int NT, int STAGE>
@@ -289,14 +291,18 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
             for (int e = tid; e < P.n + P.m + P.p; e += NT) P.adj[e] = T(0);
             continue;
         }
-        if constexpr (sizeof(T) == 4) {
-            const int stage = bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit);
-            if (stage == 2)
-                bwd_solve_mixed<NT, 2>(P, smem_raw, L.refine_steps);
-            else if (stage == 1)
-                bwd_solve_mixed<NT, 1>(P, smem_raw, L.refine_steps);
-            else
-                bwd_solve_mixed<NT, 0>(P, smem_raw, L.refine_steps);
+        bool mixed = false;
+        if constexpr (sizeof(T) == 4) mixed = (L.flags & QP_FLAG_BWD_FP32) == 0;
+        if (mixed) {
+            if constexpr (sizeof(T) == 4) {
+                const int stage = bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit);
+                if (stage == 2)
+                    bwd_solve_mixed<NT, 2>(P, smem_raw, L.refine_steps);
+                else if (stage == 1)
+                    bwd_solve_mixed<NT, 1>(P, smem_raw, L.refine_steps);
+                else
+                    bwd_solve_mixed<NT, 0>(P, smem_raw, L.refine_steps);
+            }
         } else {
         const int n = P.n, m = P.m, p = P.p;
         const BwdLayout Lo(n, m, p);
@@ -306,7 +312,7 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         const T *Wt = (const T *)(P.state + SL.off_Wt);
         const T *US = (const T *)(P.state + SL.off_US);
         const T *__restrict__ Q = P.Q;
-        const bool sg = bwd_stage_g64(n, m, p, L.lds_limit);
+        const bool sg = bwd_stage_g(sizeof(T), n, m, p, L.lds_limit);
         if (sg) {
             T *gs = sm + Lo.end;
             for (int e = tid; e < m * n; e += NT) gs[e] = P.G[e];
@@ -394,9 +400,10 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
             for (int k = tid; k < p; k += NT) dn[k] += en[k];
             __syncthreads();
             {
-                const T xs = fmax(-nx, T(1e-300));
+                // the target: 1e-8 of the solution in FP64, 1e-4 in FP32
+                const T xs = fmax(-nx, sizeof(T) == 8 ? T(1e-300) : T(1e-30));
                 const T rho = r == 0 ? emax / xs : emax / prev_applied;
-                if (emax * rho <= T(1e-8) * xs) break;
+                if (emax * rho <= (sizeof(T) == 8 ? T(1e-8) : T(1e-4)) * xs) break;
             }
             prev_applied = emax;
         }

@@ -89,6 +89,7 @@ struct BwdLaunch {
     size_t adj_stride;        // uniform mode: elements per problem (varlen mode: problem j at
                               // desc.z + desc.lam + desc.nu, the prefix sum of nz + nineq + neq)
     int refine_steps;
+    unsigned flags;           // QP_FLAG_* of the call (QP_FLAG_BWD_FP32)
     int lds_bytes;
     int lds_limit;            // device LDS per workgroup (per-problem plans depend on it only)
     int max_rows;             // largest nz + nineq + neq + 1 of the launch
@@ -107,7 +108,7 @@ int fwd_resident_workgroups(qp_dtype dt, int lds_bytes, bool with_elim);
 
 // Dynamic LDS bytes a problem needs in the backward kernel on a device with
 // `lds_limit` bytes per workgroup (FP32 stages Q, G and A there when they fit).
-size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit);
+size_t bwd_vec_lds_bytes(int esz, int n, int m, int p, int lds_limit, unsigned flags);
 
 hipError_t launch_forward(qp_dtype dt, const FwdLaunch &L, hipStream_t st);
 hipError_t launch_backward(qp_dtype dt, const BwdLaunch &L, hipStream_t st);

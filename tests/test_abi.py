@@ -108,9 +108,9 @@ def test_forward_argument_errors_before_launch():
     d.sQ = 16
     bad = binding.qp_opts()
     lib.qp_default_opts(binding.QP_F64, ctypes.byref(bad))
-    bad.flags = 2  # an unknown bit (1 is QP_FLAG_G_UNIT_ROWS)
+    bad.flags = 4  # an unknown bit (1 is QP_FLAG_G_UNIT_ROWS, 2 QP_FLAG_BWD_FP32)
     assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(bad))) == binding.QP_EARG
-    bad.flags = binding.FLAG_G_UNIT_ROWS
+    bad.flags = binding.FLAG_G_UNIT_ROWS | binding.FLAG_BWD_FP32
     assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(bad), batch=0)) == binding.QP_OK
     bad.flags, bad.tol = 0, -1.0
     assert lib.qp_forward_batched(*args(ctypes.byref(d), ctypes.byref(bad))) == binding.QP_EARG
