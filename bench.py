@@ -413,7 +413,7 @@ def bench_sweep(args):
             print("sweep batch %s B=%d: %s" % (dt, B, r), file=sys.stderr, flush=True)
     rows_box = []
     for dt in dts:
-        for n in ((60, 100) + ((200,) if dt == "f32" else ()) if "box" in parts else ()):
+        for n in ((60, 100) + ((200, 300, 500) if dt == "f32" else (300,)) if "box" in parts else ()):
             r = time_box(n, dt, steps)
             rows_box.append({"dtype": dt, "batch": 128, "nz": n, "nineq": 2 * n, **r})
             print("sweep box %s nz=%d: %s" % (dt, n, r), file=sys.stderr, flush=True)

@@ -97,12 +97,14 @@ typedef struct {
  *   -1, the rest 0), as for bounds z_j <= h_k or -z_j <= h_k (the box and
  *   non-negativity constraints of the Sudoku layer, Section 4.4, and of
  *   the ReLU layer in the proof of Theorem 2).  G is still passed densely.  The
- *   register-tile policy then forms G^T D G as a diagonal and applies G by
+ *   register-tile and streamed-tile policies then form G^T D G as a diagonal and apply G by
  *   gathers instead of products; a problem whose G does not have the structure
  *   (checked in the kernel) is solved by the dense path.  Results equal the
- *   dense path's up to rounding.  Used by qp_forward_batched for problems the
- *   register-tile policy takes; elsewhere, and in qp_forward_varlen, the flag is
- *   accepted and the dense path runs.  The backward is unchanged. */
+ *   dense path's up to rounding.  Used by the register-tile and streamed-tile
+ *   policies, in uniform and uneven batches (an uneven batch with a problem on
+ *   QP_VARIANT_ELIM runs the dense path for all); the generic and elimination-
+ *   order policies accept the flag and run the dense path.  The backward is
+ *   unchanged. */
 /* QP_FLAG_BWD_FP32: the FP32 backward computes in FP32 only: the reduced
  *   solve with the stored FP32 factor and iterative refinement on the
  *   unreduced K_sym residual in FP32 (at most refine_steps steps, ending once

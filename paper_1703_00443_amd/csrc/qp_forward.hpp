@@ -64,21 +64,24 @@ __device__ __forceinline__ void run_policy(const Prob<T> P, T *sm, const FwdLaun
     ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
 }
 
-template <typename T, bool EQ>
+template <typename T, bool EQ, bool UNIT>
 __device__ __forceinline__ void run_tiled(int pol, const Prob<T> &P, T *sm, const FwdLaunch &L) {
     if (pol == kPolicyTiledGLds) {
-        run_policy<T, TiledFactor<T, true, 8, EQ>>(P, sm, L);
+        run_policy<T, TiledFactor<T, true, 8, EQ, UNIT>>(P, sm, L);
     } else if (pol == kPolicyTiledGGlobal) {
-        run_policy<T, TiledFactor<T, false, 8, EQ>>(P, sm, L);
+        run_policy<T, TiledFactor<T, false, 8, EQ, UNIT>>(P, sm, L);
     } else if constexpr (sizeof(T) == 4) {
-        run_policy<T, TiledFactor<T, false, 16, EQ>>(P, sm, L);
+        run_policy<T, TiledFactor<T, false, 16, EQ, UNIT>>(P, sm, L);
     }
 }
 
 // ELIM: the instantiation that also carries the elimination-order policy,
 // launched only when some problem of the batch plans it (the policy's code in
-// the kernel costs the others registers).
-template <typename T, bool ELIM>
+// the kernel costs the others registers).  UNIT: the instantiation whose tiled
+// and streamed policies take the unit-row path (QP_FLAG_G_UNIT_ROWS set on the
+// call; each problem's G is still checked, and a dense G runs the dense path).
+// A call with both gets the ELIM instantiation, where the flag is not used.
+template <typename T, bool ELIM, bool UNIT>
 __global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunch L) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int next_idx;
@@ -98,11 +101,11 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunc
         int bytes = 0;
         const int pol = plan_policy(sizeof(T), P.n, P.m, P.p, P.variant, L.lds_limit, &bytes);
         if (pol == kPolicyTiledGLds || pol == kPolicyTiledGGlobal || pol == kPolicyTiledBig) {
-            if (P.p > 0) run_tiled<T, true>(pol, P, sm, L);
-            else run_tiled<T, false>(pol, P, sm, L);
+            if (P.p > 0) run_tiled<T, true, UNIT>(pol, P, sm, L);
+            else run_tiled<T, false, UNIT>(pol, P, sm, L);
         } else if (pol == kPolicyStream) {
-            if (P.p > 0) run_policy<T, StreamFactor<T, true>>(P, sm, L);
-            else run_policy<T, StreamFactor<T, false>>(P, sm, L);
+            if (P.p > 0) run_policy<T, StreamFactor<T, true, UNIT>>(P, sm, L);
+            else run_policy<T, StreamFactor<T, false, UNIT>>(P, sm, L);
         } else if (ELIM && pol == kPolicyElim) {
             if constexpr (ELIM) {
                 if (P.p > 0) run_policy<T, ElimFactor<T, true>>(P, sm, L);
@@ -157,12 +160,17 @@ static hipError_t launch_uniform_tiled_u(int pol, const FwdLaunch &L, hipStream_
     return hipErrorInvalidValue;
 }
 
-// QP_FLAG_G_UNIT_ROWS selects the unit-row instantiation (uniform batches; the
-// uneven-batch kernel runs the dense path for every problem).
+// QP_FLAG_G_UNIT_ROWS selects the unit-row instantiations.
 template <typename T, bool EQ>
 static hipError_t launch_uniform_tiled(int pol, const FwdLaunch &L, hipStream_t st) {
     if ((L.flags & QP_FLAG_G_UNIT_ROWS) && L.nineq > 0) return launch_uniform_tiled_u<T, EQ, true>(pol, L, st);
     return launch_uniform_tiled_u<T, EQ, false>(pol, L, st);
+}
+
+template <typename T, bool EQ>
+static hipError_t launch_uniform_stream(const FwdLaunch &L, hipStream_t st) {
+    if ((L.flags & QP_FLAG_G_UNIT_ROWS) && L.nineq > 0) return launch_uniform<T, StreamFactor<T, EQ, true>>(L, st);
+    return launch_uniform<T, StreamFactor<T, EQ, false>>(L, st);
 }
 
 __global__ void qp_zero_counter_kernel(int *c);
@@ -177,17 +185,19 @@ hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
             return L.neq > 0 ? launch_uniform_tiled<T, true>(pol, L, st)
                              : launch_uniform_tiled<T, false>(pol, L, st);
         if (pol == kPolicyStream)
-            return L.neq > 0 ? launch_uniform<T, StreamFactor<T, true>>(L, st)
-                             : launch_uniform<T, StreamFactor<T, false>>(L, st);
+            return L.neq > 0 ? launch_uniform_stream<T, true>(L, st) : launch_uniform_stream<T, false>(L, st);
         if (pol == kPolicyElim)
             return L.neq > 0 ? launch_uniform<T, ElimFactor<T, true>>(L, st)
                              : launch_uniform<T, ElimFactor<T, false>>(L, st);
         if (pol == kPolicyGenericLds) return launch_uniform<T, GenericFactor<T, kFwdThreads, true>>(L, st);
         return launch_uniform<T, GenericFactor<T, kFwdThreads, false>>(L, st);
     }
-    auto kern = L.with_elim ? qp_forward_varlen_kernel<T, true> : qp_forward_varlen_kernel<T, false>;
-    if (L.with_elim) set_lds_limit_once<qp_forward_varlen_kernel<T, true>>(L.lds_limit);
-    else set_lds_limit_once<qp_forward_varlen_kernel<T, false>>(L.lds_limit);
+    const bool unit = !L.with_elim && (L.flags & QP_FLAG_G_UNIT_ROWS) != 0;
+    auto kern = L.with_elim ? qp_forward_varlen_kernel<T, true, false>
+                            : unit ? qp_forward_varlen_kernel<T, false, true> : qp_forward_varlen_kernel<T, false, false>;
+    if (L.with_elim) set_lds_limit_once<qp_forward_varlen_kernel<T, true, false>>(L.lds_limit);
+    else if (unit) set_lds_limit_once<qp_forward_varlen_kernel<T, false, true>>(L.lds_limit);
+    else set_lds_limit_once<qp_forward_varlen_kernel<T, false, false>>(L.lds_limit);
     if (L.queue) {
         hipLaunchKernelGGL(qp_zero_counter_kernel, dim3(1), dim3(1), 0, st, L.queue);
         const hipError_t e = hipGetLastError();
@@ -204,9 +214,9 @@ int resident_t(int lds_bytes, bool with_elim) {
     if (hipGetDevice(&dev) != hipSuccess) return 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
     const hipError_t e =
-        with_elim ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T, true>,
+        with_elim ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T, true, false>,
                                                                  kFwdThreads, (size_t)lds_bytes)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T, false>,
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, qp_forward_varlen_kernel<T, false, false>,
                                                                  kFwdThreads, (size_t)lds_bytes);
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;

@@ -263,6 +263,87 @@ __device__ __forceinline__ bool diag_chol_inv16(T *pan, int lane, T *x) {
     return !bad;
 }
 
+// Rows of G that are signed unit vectors (QP_FLAG_G_UNIT_ROWS): row k has its
+// one entry sign[k] in column col[k]; the rows of column j, in order, are
+// row[off[j] .. off[j+1]).  The arrays take 3 nineq + nz + 1 elements of T
+// from the region given to place().
+template <typename T, int NT>
+struct UnitRows {
+    T *sign;
+    int *col, *off, *row;
+
+    __host__ __device__ static constexpr int elems(int n, int m) { return 3 * m + n + 1; }
+    __device__ __forceinline__ void place(T *region, int n, int m) {
+        sign = region;
+        col = reinterpret_cast<int *>(region + m);
+        off = col + m;
+        row = off + n + 1;
+    }
+    // Finds each row's one entry; false (uniformly) if some row is not a signed
+    // unit vector, true once the per-column row lists are built.
+    __device__ __forceinline__ bool detect(const T *G, int n, int m, T *red) {
+        T bad = 0, d0 = 0, d1 = 0;
+        for (int k = threadIdx.x; k < m; k += NT) {
+            int cj = 0, cnt = 0;
+            T val = 0;
+            for (int j = 0; j < n; ++j) {
+                const T v = G[(size_t)k * n + j];
+                if (v != T(0)) { ++cnt; cj = j; val = v; }
+            }
+            if (cnt != 1 || !(val == T(1) || val == T(-1))) bad = 1;
+            col[k] = cj;
+            sign[k] = val;
+        }
+        block_reduce3<T, NT>(bad, d0, d1, red);
+        if (bad != T(0)) return false;
+        // rows per column, offsets (one thread), rows in order
+        for (int j = threadIdx.x; j < n; j += NT) {
+            int cnt = 0;
+            for (int k = 0; k < m; ++k) cnt += col[k] == j;
+            off[j + 1] = cnt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            off[0] = 0;
+            for (int j = 0; j < n; ++j) off[j + 1] += off[j];
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += NT) {
+            int o = off[j];
+            for (int k = 0; k < m; ++k)
+                if (col[k] == j) row[o++] = k;
+        }
+        __syncthreads();
+        return true;
+    }
+    // out[j] = sum of D over the rows of column j (the diagonal G^T D G), in row order
+    __device__ __forceinline__ void diag(const T *D, T *out, int n) const {
+        for (int j = threadIdx.x; j < n; j += NT) {
+            T a = 0;
+            for (int t = off[j]; t < off[j + 1]; ++t) a += D[row[t]];
+            out[j] = a;
+        }
+        __syncthreads();
+    }
+    // out = G^T v
+    __device__ __forceinline__ void gt(const T *v, T *out, int n) const {
+        for (int j = threadIdx.x; j < n; j += NT) {
+            T a = 0;
+            for (int t = off[j]; t < off[j + 1]; ++t) {
+                const int k = row[t];
+                a += sign[k] * v[k];
+            }
+            out[j] = a;
+        }
+        __syncthreads();
+    }
+    // out = G x
+    __device__ __forceinline__ void g(const T *x, T *out, int m) const {
+        for (int k = threadIdx.x; k < m; k += NT) out[k] = sign[k] * x[col[k]];
+        __syncthreads();
+    }
+};
+
 // Which tiles a wavefront holds (see the grid comment above).
 template <int NTL>
 struct TileMap {
@@ -291,12 +372,9 @@ struct TiledFactor {
     T *part, *yv, *xv, *panel, *scratch, *S, *xdp, *pv1, *pv2;
     int *flag;
     int w, lane, g, c;
-    // rows of G that are signed unit vectors (QP_FLAG_G_UNIT_ROWS): row k has
-    // its one entry usign[k] in column ucol[k]; the rows of column j, in
-    // order, are urow[uoff[j] .. uoff[j+1]).  All live in the G region.
+    // rows of G that are signed unit vectors (QP_FLAG_G_UNIT_ROWS), in the G region
     bool unit;
-    int *ucol, *uoff, *urow;
-    T *usign;
+    UnitRows<T, NT> ur;
     v4 sq[NS];
 
     __device__ __forceinline__ int trow(int s) const { return TileMap<NTL>::row(s); }
@@ -324,11 +402,9 @@ struct TiledFactor {
         G = sm + L.G; ldg = np + 1; lds = h_ld(p); ldu = u_ld(n);
         lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
         const int gcap = (GL ? ((m + 3) & ~3) : kGChunk) * (np + 1);
-        unit = UNIT && (P.flags & QP_FLAG_G_UNIT_ROWS) != 0 && m > 0 && 3 * m + n + 1 <= gcap;
-        usign = sm + L.G;
-        ucol = reinterpret_cast<int *>(sm + L.G + m);
-        uoff = ucol + m;
-        urow = uoff + n + 1;
+        unit = UNIT && (P.flags & QP_FLAG_G_UNIT_ROWS) != 0 && m > 0 &&
+               UnitRows<T, NT>::elems(n, m) <= gcap;
+        ur.place(sm + L.G, n, m);
     }
 
     // Rows [k0, k0 + rows) of G into the LDS buffer, zero-padded to whole MFMA
@@ -347,42 +423,8 @@ struct TiledFactor {
     // loads in form() and qs_mv().  With equality rows the Schur step stores U there every
     // factorization, and Qs is taken from Q itself.
     __device__ __forceinline__ void prepare() {
-        if (UNIT && unit) {
-            // find each row's one entry; any other row sends the problem down the dense path
-            T bad = 0, d0 = 0, d1 = 0;
-            for (int k = threadIdx.x; k < m; k += NT) {
-                int col = 0, cnt = 0;
-                T val = 0;
-                for (int j = 0; j < n; ++j) {
-                    const T v = Gsrc[(size_t)k * n + j];
-                    if (v != T(0)) { ++cnt; col = j; val = v; }
-                }
-                if (cnt != 1 || !(val == T(1) || val == T(-1))) bad = 1;
-                ucol[k] = col;
-                usign[k] = val;
-            }
-            block_reduce3<T, NT>(bad, d0, d1, scratch);
-            unit = bad == T(0);
-            if (unit) {
-                // rows per column, offsets (one thread; n is small), rows in order
-                for (int j = threadIdx.x; j < n; j += NT) {
-                    int cnt = 0;
-                    for (int k = 0; k < m; ++k) cnt += ucol[k] == j;
-                    uoff[j + 1] = cnt;
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    uoff[0] = 0;
-                    for (int j = 0; j < n; ++j) uoff[j + 1] += uoff[j];
-                }
-                __syncthreads();
-                for (int j = threadIdx.x; j < n; j += NT) {
-                    int o = uoff[j];
-                    for (int k = 0; k < m; ++k)
-                        if (ucol[k] == j) urow[o++] = k;
-                }
-            }
-        }
+        // any row that is not a signed unit vector sends the problem down the dense path
+        if (UNIT && unit) unit = ur.detect(Gsrc, n, m, scratch);
         if (!EQ)
             for (int e = threadIdx.x; e < n * n; e += NT) {
                 const int i = e / n, j = e - i * n;
@@ -397,15 +439,7 @@ struct TiledFactor {
     // k loop runs outside the tile loop so that the MFMAs of the tiles of a
     // wavefront are independent and overlap their operand loads.
     __device__ __forceinline__ void form(const T *D) {
-        if (UNIT && unit) {
-            // G^T D G is diagonal: column j sums D over its rows, in row order
-            for (int j = threadIdx.x; j < n; j += NT) {
-                T a = 0;
-                for (int t = uoff[j]; t < uoff[j + 1]; ++t) a += D[urow[t]];
-                xv[j] = a;
-            }
-            __syncthreads();
-        }
+        if (UNIT && unit) ur.diag(D, xv, n);  // G^T D G is diagonal
         lane_ids();
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -767,15 +801,7 @@ struct TiledFactor {
     }
     __device__ __forceinline__ void gt_mv(const T *v, T *out) {
         if (UNIT && unit) {
-            for (int j = threadIdx.x; j < n; j += NT) {
-                T a = 0;
-                for (int t = uoff[j]; t < uoff[j + 1]; ++t) {
-                    const int k = urow[t];
-                    a += usign[k] * v[k];
-                }
-                out[j] = a;
-            }
-            __syncthreads();
+            ur.gt(v, out, n);
             return;
         }
         if (GL) colsum(G, ldg, m, n, v, out);
@@ -783,8 +809,7 @@ struct TiledFactor {
     }
     __device__ __forceinline__ void g_mv(const T *x, T *out) {
         if (UNIT && unit) {
-            for (int k = threadIdx.x; k < m; k += NT) out[k] = usign[k] * x[ucol[k]];
-            __syncthreads();
+            ur.g(x, out, m);
             return;
         }
         if (GL) {

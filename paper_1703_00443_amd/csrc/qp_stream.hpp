@@ -13,6 +13,10 @@
 //          state, four MFMAs, stored back), four tiles in flight per wavefront.
 //   solve: triangular matrix-vector products over the stored U.
 //   Schur complement on A (equality rows): as in the tiled policy.
+//   UNIT (QP_FLAG_G_UNIT_ROWS, a separate instantiation): G^T D G is the
+//          diagonal of per-column sums of D (no G streaming), and products with
+//          G are gathers; the row lists sit in the staging region after the
+//          Schur block, which neither the factorization nor the solves use.
 #pragma once
 #include "qp_policies.hpp"
 
@@ -56,7 +60,7 @@ __host__ __device__ inline bool stream_plan(int esz, int base, int n, int m, int
     return false;
 }
 
-template <typename T, bool EQ>
+template <typename T, bool EQ, bool UNIT = false>
 struct StreamFactor {
     static constexpr bool kRefineAlways = false;
     static constexpr bool kSolveGz = false;
@@ -71,6 +75,8 @@ struct StreamFactor {
     T *yv, *xv, *panel, *scratch, *xdp, *pv1, *pv2, *gbuf, *S;
     int fcap;  // form(): elements from the panel to the end of the layout (idle during the formation)
     int *flag;
+    bool unit;
+    UnitRows<T, NT> ur;
     int w, lane, g, c;
 
     __device__ __forceinline__ void lane_ids() {
@@ -99,9 +105,15 @@ struct StreamFactor {
         ldg = np + 1; ldu = u_ld(n);
         if (s_lds) { S = sm + L.buf; lds = h_ld(p); } else { S = US; lds = p; }
         lane = threadIdx.x & 63; w = threadIdx.x >> 6; g = lane >> 4; c = lane & 15;
+        const int uo = L.buf + ((EQ && s_lds) ? p * h_ld(p) : 0);
+        unit = UNIT && (P.flags & QP_FLAG_G_UNIT_ROWS) != 0 && m > 0 &&
+               uo + UnitRows<T, NT>::elems(n, m) <= L.end;
+        ur.place(sm + uo, n, m);
     }
 
-    __device__ __forceinline__ void prepare() {}
+    __device__ __forceinline__ void prepare() {
+        if (UNIT && unit) unit = ur.detect(Gsrc, n, m, scratch);
+    }
 
     // Lower tile t (row-major order over the lower triangle of the tile grid).
     __device__ __forceinline__ static void lower_tile(int t, int &I, int &J) {
@@ -113,6 +125,7 @@ struct StreamFactor {
     }
 
     __device__ __forceinline__ void form(const T *D) {
+        if (UNIT && unit) ur.diag(D, xv, n);  // G^T D G is diagonal
         lane_ids();
         // upper tiles start at zero (they become X^T = L^{-T} strictly above the diagonal)
         for (int t = w; t < nt * nt; t += kTiledWaves) {
@@ -151,12 +164,14 @@ struct StreamFactor {
                         const bool in = row < n && col < n;
                         const T qa = Q[in ? (size_t)row * n + col : 0];
                         const T qb = Q[in ? (size_t)col * n + row : 0];
-                        a[r] = in ? T(0.5) * (qa + qb) : (row == col ? T(1) : T(0));
+                        T qs = T(0.5) * (qa + qb);
+                        if (UNIT && unit && in && row == col) qs += xv[row];
+                        a[r] = in ? qs : (row == col ? T(1) : T(0));
                     }
                 }
                 acc[j] = a;
             }
-            for (int k0 = 0; k0 < m; k0 += kcr) {
+            for (int k0 = 0; k0 < ((UNIT && unit) ? 0 : m); k0 += kcr) {
                 const int rows = min(kcr, m - k0), rp = (rows + 3) & ~3;
                 // all SE loads of this thread are issued before any store
                 T stg[SE];
@@ -391,9 +406,17 @@ struct StreamFactor {
     }
 
     __device__ __forceinline__ void gt_mv(const T *v, T *out) {
+        if (UNIT && unit) {
+            ur.gt(v, out, n);
+            return;
+        }
         colsum_split<T, NT>(Gsrc, n, m, n, v, out, scratch);
     }
     __device__ __forceinline__ void g_mv(const T *x, T *out) {
+        if (UNIT && unit) {
+            ur.g(x, out, m);
+            return;
+        }
         mv_rows<T, NT>(Gsrc, n, m, n, x, out);
         __syncthreads();
     }

@@ -264,6 +264,68 @@ def test_unit_row_flag_box_qp(n):
                 assert z_err(fast["z"][i], dense["z"][i]) <= TOL_Z[dtype]
 
 
+@pytest.mark.parametrize("n", [300, 500])
+def test_unit_row_flag_streamed_policy(n):
+    """QP_FLAG_G_UNIT_ROWS on box QPs above the register-tile limits, where the
+    streamed-tile policy runs: G^T D G as a diagonal, products with G as
+    gathers.  z and lambda close to the dense path's result (where the step
+    counts agree; FP64 and FP32 at nz = 300, FP32 at nz = 500), and at nz = 300
+    every output and gradient of one problem against the oracle replay."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    b = synth.box_batch(seed=3030 + n, B=2, n=n)
+    # FP64 at nz = 500 with 1000 rows: the driver's vectors alone leave no room
+    # for the streamed layout, so the generic policy runs (no unit-row path)
+    for dtype in ((np.float64, np.float32) if n <= 300 else (np.float32,)):
+        tdt = torch.float64 if dtype == np.float64 else torch.float32
+        assert qb.plan(tdt, n, 2 * n, 0)[0] == qb.VARIANT_STREAM
+        fast = _run(b, dtype, opts_over={"flags": qb.FLAG_G_UNIT_ROWS})
+        dense = _run(b, dtype)
+        assert np.all(np.isin(fast["status"], (0, 1, 4))), fast["status"]
+        for i in range(2):
+            if fast["iters"][i] == dense["iters"][i]:
+                assert z_err(fast["z"][i], dense["z"][i]) <= TOL_Z[dtype]
+                assert z_err(fast["lam"][i], dense["lam"][i]) <= TOL_Z[dtype] * 10
+        if n == 300:
+            _check(b, fast, dtype, range(1), tag="box_stream%d" % n)
+
+
+def test_unit_row_flag_in_uneven_batch():
+    """Box QPs of sizes from 20 to 300 in one uneven launch with the flag set
+    (register-tile and streamed policies, the unit-row instantiation of the
+    persistent kernel), next to a dense-G problem: each result bitwise equal to
+    the same problem solved alone with the flag, z of every box problem within
+    tolerance of the dense path's, and z of the smaller ones against the oracle."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd.varlen import VarlenBatch
+    from parity import oracle_replay
+    sizes = [20, 64, 150, 300, 90]
+    probs = [synth.box_batch(seed=5050 + n, B=1, n=n).problem(0) for n in sizes]
+    probs.append(synth.make_batch(seed=5051, B=1, n=40, m=60, p=3).problem(0))
+    for dtype in (np.float32, np.float64):
+        tdt = torch.float64 if dtype == np.float64 else torch.float32
+        ps = [{k: (None if v is None else np.asarray(v, dtype)) for k, v in P.items()} for P in probs]
+        flag = qb.default_opts(tdt, flags=qb.FLAG_G_UNIT_ROWS)
+        vb = VarlenBatch(ps, dtype=tdt)
+        vb.forward(flag)
+        dense = VarlenBatch(ps, dtype=tdt)
+        dense.forward()
+        torch.cuda.synchronize()
+        for i, P in enumerate(ps):
+            one = VarlenBatch([P], dtype=tdt)
+            one.forward(flag)
+            torch.cuda.synchronize()
+            r, a, d = vb.result(i), one.result(0), dense.result(i)
+            np.testing.assert_array_equal(r["z"], a["z"])
+            assert int(r["status"]) in (0, 1, 4)
+            if r["iters"] == d["iters"]:
+                assert z_err(r["z"], d["z"]) <= TOL_Z[dtype]
+            if P["Q"].shape[0] <= 90:
+                ref = oracle_replay(probs[i], int(r["iters"]), dtype)
+                assert z_err(r["z"], ref["z"]) <= TOL_Z[dtype], (dtype, i)
+
+
 def test_unit_row_flag_falls_back_on_dense_g():
     """With the flag set but a G whose rows are not signed unit vectors, the
     kernel takes the dense path: bitwise the unflagged result."""

@@ -198,9 +198,11 @@ def test_uneven_4096_stratified_256_vs_oracle():
             assert rec["kkt"] <= 10 * 1e-3 and rec["z_vs_converged"] <= 2e-2, rec
 
 
-def test_unit_row_flag_is_accepted_and_dense_in_uneven_batches():
-    """qp_forward_varlen accepts QP_FLAG_G_UNIT_ROWS and runs the dense path for
-    every problem: bitwise the unflagged result (box QPs of two sizes)."""
+def test_unit_row_flag_dense_in_uneven_batches_with_elimination_order():
+    """An uneven batch that holds a problem on the elimination order runs the
+    persistent kernel instantiation without the unit-row path: with
+    QP_FLAG_G_UNIT_ROWS set, every result is bitwise the unflagged one (box QPs
+    of two sizes next to a problem that requests QP_VARIANT_ELIM)."""
     import torch
     from paper_1703_00443_amd import binding as qb
     from paper_1703_00443_amd.varlen import VarlenBatch
@@ -211,8 +213,10 @@ def test_unit_row_flag_is_accepted_and_dense_in_uneven_batches():
             P = b.problem(i)
             P["A"], P["b"] = None, None
             probs.append(P)
-    a = VarlenBatch(probs, dtype=torch.float32)
-    d = VarlenBatch(probs, dtype=torch.float32)
+    probs.append(synth.make_batch(seed=9, B=1, n=50, m=20, p=0).problem(0))
+    variants = [0] * 4 + [qb.VARIANT_ELIM]
+    a = VarlenBatch(probs, dtype=torch.float32, variants=variants)
+    d = VarlenBatch(probs, dtype=torch.float32, variants=variants)
     a.forward(qb.default_opts(torch.float32, flags=qb.FLAG_G_UNIT_ROWS))
     d.forward()
     torch.cuda.synchronize()
