@@ -41,9 +41,11 @@ namespace qpmi {
 struct ElimLayout {
     int vh, ldv, zz, ldz, cdg, dinv, u, xi, tn3, nu0, g1, wv, t1, t2, scr, end;
     __host__ __device__ ElimLayout(int base, int n, int m, int p) {
-        const TiledLayout<true> Ls(base, m, 0, 0);
+        // the nineq x nineq factor is seeded, never formed: its G staging
+        // region (the end of its layout) is not used, and Vh starts there
+        const TiledLayout<false> Ls(base, m, 0, 0);
         const int N = pad4(n), M = pad4(m), Pp = pad4(p);
-        int o = Ls.end;
+        int o = Ls.G;
         ldv = n | 1; vh = o; o += m * ldv;
         ldz = Pp; zz = o; o += m * ldz;
         cdg = o; o += M;
@@ -88,6 +90,10 @@ __device__ __forceinline__ void tile_product(int rows, int cols, int kdim, bool 
     __syncthreads();
 }
 
+// One register-tile factor object serves all three factorizations (Qs once,
+// C + D^{-1} every Newton step, H at the end), re-aimed between the nz x nz
+// and the nineq x nineq sizes: separate objects for them kept three sets of
+// register tiles alive and spilled to scratch memory.
 template <typename T, bool EQ>
 struct ElimFactor {
     static constexpr int NT = 64 * kTiledWaves;
@@ -102,9 +108,7 @@ struct ElimFactor {
     // the solve yields w = D G dz directly (the paper's unknown in the
     // nineq x nineq system); solve_g returns D^{-1} w for G dz
     static constexpr bool kSolveGz = true;
-    using Dense = TiledFactor<T, false, 8, EQ, false>;  // Qs (prepare) and H (finish), nz x nz
-    using Small = TiledFactor<T, true, 8, false, false>; // C + D^{-1}, nineq x nineq
-    Prob<T> Pr;
+    using TF = TiledFactor<T, false, 8, EQ, false>;
     T *sm;
     int base;
     int n, m, p, ldu, ldv, ldz;
@@ -113,16 +117,10 @@ struct ElimFactor {
     T *vh, *zz, *cdg, *dinv, *u, *xi, *tn3, *nu0, *g1, *wv, *t1, *t2, *scr;
     const T *Dcur;  // the scaling of the last factor() call
     bool bad;
-    Small sf;
-
-    __device__ __forceinline__ static Prob<T> small_prob(const Prob<T> &P) {
-        Prob<T> S = P;
-        S.n = P.m; S.m = 0; S.p = 0; S.flags = 0;
-        return S;
-    }
+    TF tf;  // nz x nz in prepare() and finish(), nineq x nineq in between
 
     __device__ __forceinline__ ElimFactor(const Prob<T> &P, T *sm_, int base_)
-        : Pr(P), sm(sm_), base(base_), sf(small_prob(P), sm_, base_) {
+        : sm(sm_), base(base_), tf(P, sm_, base_) {
         n = P.n; m = P.m; p = P.p;
         Q = P.Q; G = P.G;
         const StateLayout SL = state_layout(sizeof(T), n, m, p);
@@ -142,17 +140,16 @@ struct ElimFactor {
     // below U_Q in the state and its diagonal in LDS.
     __device__ __forceinline__ void prepare() {
         {
-            Dense qf(Pr, sm, base);
-            qf.m = 0;          // H = Qs: no rows of G
-            qf.prepare();      // no equality rows: Qs staged in the state's U region
-            bool ok = qf.factor(nullptr);  // with equality rows: U_Q, At and S_A too
+            tf.retarget(n, 0, p, sm, base);  // H = Qs: no rows of G
+            tf.prepare();      // no equality rows: Qs staged in the state's U region
+            bool ok = tf.factor(nullptr);  // with equality rows: U_Q, At and S_A too
             if constexpr (!EQ) {
-                if (ok) qf.store_u();
+                if (ok) tf.store_u();
             } else {
                 if (ok)
                     for (int e = threadIdx.x; e < p * p; e += NT) {
                         const int i = e / p, j = e - i * p;
-                        US[e] = qf.S[i * qf.lds + j];
+                        US[e] = tf.S[i * tf.lds + j];
                     }
             }
             __syncthreads();
@@ -243,6 +240,7 @@ struct ElimFactor {
                 if (i > j) cp[(size_t)i * lu + j] = v;
                 else if (i == j) dp[i] = v;
             });
+        tf.retarget(m, 0, 0, sm, base);  // the nineq x nineq factor from here on
     }
 
     // Per iterate: C + D^{-1} into the register tiles, Cholesky and inverse.
@@ -252,8 +250,8 @@ struct ElimFactor {
         if (m == 0) return true;
         for (int k = threadIdx.x; k < m; k += NT) dinv[k] = cdg[k] + T(1) / D[k];
         __syncthreads();
-        sf.seed(Ust, ldu, dinv);
-        return sf.chol_inv();
+        tf.seed(Ust, ldu, dinv);
+        return tf.chol_inv();
     }
 
     __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
@@ -286,7 +284,7 @@ struct ElimFactor {
                 }
                 __syncthreads();
             }
-            sf.solve(g1, nullptr, wv, nullptr);               // w = (C + D^{-1})^{-1} g1
+            tf.solve(g1, nullptr, wv, nullptr);               // w = (C + D^{-1})^{-1} g1 (p = 0 here)
             colsum_split<T, NT>(vh, ldv, m, n, wv, tn3, scr);  // Vh^T w
             for (int i = threadIdx.x; i < n; i += NT) tn3[i] = x0[i] - tn3[i];
             if constexpr (EQ)
@@ -332,9 +330,9 @@ struct ElimFactor {
     // factor can stay positive definite at iterates where H no longer is in
     // working precision; false then (the driver returns the previous iterate).
     __device__ __forceinline__ bool finish(const T *D) {
-        Dense hf(Pr, sm, base);
-        hf.prepare();
-        return hf.factor(D) && hf.finish(D);
+        tf.retarget(n, m, p, sm, base);
+        tf.prepare();
+        return tf.factor(D) && tf.finish(D);
     }
 };
 

@@ -407,6 +407,21 @@ struct TiledFactor {
         ur.place(sm + L.G, n, m);
     }
 
+    // Re-aims the object at an n_ x n_ factor with m_ rows of G and p_ equality
+    // rows whose LDS regions start at `base` (the problem's inputs and state
+    // pointers, and ldu, stay as constructed).  One object can then factor
+    // matrices of two sizes in turn with the same register tiles.
+    __device__ __forceinline__ void retarget(int n_, int m_, int p_, T *sm, int base) {
+        n = n_; m = m_; p = p_;
+        nt = (n + 15) / 16; np = 16 * nt; pt = (p + 15) / 16;
+        const TiledLayout<GL> L(base, n, m, p);
+        part = sm + L.part; yv = sm + L.yv; xv = sm + L.xv;
+        panel = sm + L.panel; scratch = sm + L.scratch;
+        S = sm + L.S; xdp = sm + L.xdp; pv1 = sm + L.pv1; pv2 = sm + L.pv2;
+        flag = reinterpret_cast<int *>(sm + L.flag);
+        G = sm + L.G; ldg = np + 1; lds = h_ld(p);
+    }
+
     // Rows [k0, k0 + rows) of G into the LDS buffer, zero-padded to whole MFMA
     // steps (rows to a multiple of 4, columns to 16 nt).
     __device__ __forceinline__ void stage_g(int k0, int rows) {
