@@ -57,9 +57,8 @@ enum {
     QP_STATUS_OPTIMAL = 0,   /* stopping test met (see qp_opts.tol)                     */
     QP_STATUS_MAX_ITER = 1,  /* max_iter Newton steps taken; last iterate returned      */
     QP_STATUS_BREAKDOWN = 2, /* non-positive or non-finite pivot in the factorization of
-                                the initial point or the first iterate (QP_VARIANT_ELIM:
-                                also of Qs); no factor is stored and the backward writes
-                                zero gradients                                           */
+                                the initial point or the first iterate; no factor is
+                                stored and the backward writes zero gradients            */
     QP_STATUS_NONFINITE = 3, /* non-finite input or iterate; no factor is stored and the
                                 backward writes zero gradients                           */
     QP_STATUS_STALLED = 4    /* the factorization of the next iterate lost positive
@@ -126,8 +125,9 @@ enum {
                                (neq x neq) factored once per solve, only an nineq x nineq
                                matrix C + D(s / lambda), C = G M G^T with M the inverse of
                                [Qs A^T; A 0] restricted to z, factored per Newton step.
-                               Requires Qs positive definite (otherwise BREAKDOWN),
-                               nz <= 128, nineq <= nz rounded up to a multiple of 16, and
+                               Where Qs is not positive definite the problem is solved
+                               by the register-tile policy.  Applies for nz <= 128,
+                               nineq <= nz rounded up to a multiple of 16, and
                                its LDS regions (G U_Q among them) fitting; elsewhere the
                                automatic plan runs.  Cheaper per step than forming H where
                                nineq < nz.  The forward ends by factoring H at the returned

@@ -23,10 +23,11 @@
 // which is the same solution as the policies that factor H, up to rounding.
 // C + D^{-1} is factored with the register-tile Cholesky of the tiled policy.
 //
-// Requires Qs positive definite (and A of full row rank): otherwise the first
-// factor call fails and the problem ends BREAKDOWN.  The factor kept for the
-// backward is the one the other policies keep (H at the returned iterate): it
-// is formed and factored once more in finish(), so the backward is shared.
+// The caller factors Qs first (factor_qs); where that fails (Qs not positive
+// definite in working precision) it solves the problem with the tiled policy
+// instead.  The factor kept for the backward is the one the other policies
+// keep (H at the returned iterate): it is formed and factored once more in
+// finish(), so the backward is shared.
 #pragma once
 #include "qp_policies.hpp"
 
@@ -116,8 +117,7 @@ struct ElimFactor {
     T *Ust, *Wt, *US;
     T *vh, *zz, *cdg, *dinv, *u, *xi, *tn3, *nu0, *g1, *wv, *t1, *t2, *scr;
     const T *Dcur;  // the scaling of the last factor() call
-    bool bad;
-    TF tf;  // nz x nz in prepare() and finish(), nineq x nineq in between
+    TF tf;  // nz x nz in factor_qs(), prepare() and finish(), nineq x nineq in between
 
     __device__ __forceinline__ ElimFactor(const Prob<T> &P, T *sm_, int base_)
         : sm(sm_), base(base_), tf(P, sm_, base_) {
@@ -133,29 +133,31 @@ struct ElimFactor {
         vh = sm + L.vh; zz = sm + L.zz; cdg = sm + L.cdg; dinv = sm + L.dinv;
         u = sm + L.u; xi = sm + L.xi; tn3 = sm + L.tn3; nu0 = sm + L.nu0; g1 = sm + L.g1;
         wv = sm + L.wv; t1 = sm + L.t1; t2 = sm + L.t2; scr = sm + L.scr;
-        bad = false;
     }
 
-    // Once per solve: U_Q, At and U_A into the state; Vh and Z into LDS; C
-    // below U_Q in the state and its diagonal in LDS.
-    __device__ __forceinline__ void prepare() {
-        {
-            tf.retarget(n, 0, p, sm, base);  // H = Qs: no rows of G
-            tf.prepare();      // no equality rows: Qs staged in the state's U region
-            bool ok = tf.factor(nullptr);  // with equality rows: U_Q, At and S_A too
-            if constexpr (!EQ) {
-                if (ok) tf.store_u();
-            } else {
-                if (ok)
-                    for (int e = threadIdx.x; e < p * p; e += NT) {
-                        const int i = e / p, j = e - i * p;
-                        US[e] = tf.S[i * tf.lds + j];
-                    }
-            }
-            __syncthreads();
-            bad = !ok;
+    // Once per solve, before the driver starts: U_Q, At and U_A into the
+    // state.  False (uniformly) when Qs or A's Schur complement does not factor.
+    __device__ __forceinline__ bool factor_qs() {
+        tf.retarget(n, 0, p, sm, base);  // H = Qs: no rows of G
+        tf.prepare();                     // no equality rows: Qs staged in the state's U region
+        const bool ok = tf.factor(nullptr);  // with equality rows: U_Q, At and S_A too
+        if constexpr (!EQ) {
+            if (ok) tf.store_u();
+        } else {
+            if (ok)
+                for (int e = threadIdx.x; e < p * p; e += NT) {
+                    const int i = e / p, j = e - i * p;
+                    US[e] = tf.S[i * tf.lds + j];
+                }
         }
-        if (bad || m == 0) return;
+        __syncthreads();
+        return ok;
+    }
+
+    // The driver's once-per-solve step: Vh and Z into LDS; C below U_Q in the
+    // state and its diagonal in LDS.
+    __device__ __forceinline__ void prepare() {
+        if (m == 0) return;
         const T *Gp = G, *Up = Ust;
         T *vp = vh;
         const int nn = n, mm = m, lu = ldu, lv = ldv;
@@ -245,7 +247,6 @@ struct ElimFactor {
 
     // Per iterate: C + D^{-1} into the register tiles, Cholesky and inverse.
     __device__ __forceinline__ bool factor(const T *D) {
-        if (bad) return false;
         Dcur = D;
         if (m == 0) return true;
         for (int k = threadIdx.x; k < m; k += NT) dinv[k] = cdg[k] + T(1) / D[k];

@@ -20,8 +20,8 @@ __host__ __device__ inline int plan_policy(int esz, int n, int m, int p, int var
                                            int *lds_bytes) {
     const int base = IpmLayout(n, m, p).end;
     if (variant == QP_VARIANT_ELIM && n <= kTiledMaxN && m <= u_ld(n)) {
-        // taken only on request (it needs Qs positive definite); where it does
-        // not apply the automatic plan runs
+        // taken on request (or from an autotune table); where it does not
+        // apply the automatic plan runs
         const int el = elim_lds_elems(base, n, m, p) * esz;
         if (el <= lds_limit) { *lds_bytes = el; return kPolicyElim; }
     }
@@ -61,6 +61,22 @@ template <typename T, class F>
 __device__ __forceinline__ void run_policy(const Prob<T> P, T *sm, const FwdLaunch &L) {
     const IpmLayout Lo(P.n, P.m, P.p);
     F f(P, sm, Lo.end);
+    ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
+}
+
+// The elimination order, or the tiled policy where Qs does not factor (the
+// decision is made before the solve, so each Newton loop is its own code).
+template <typename T, bool EQ>
+__device__ __forceinline__ void run_elim(const Prob<T> &P, T *sm, const FwdLaunch &L) {
+    const IpmLayout Lo(P.n, P.m, P.p);
+    {
+        ElimFactor<T, EQ> f(P, sm, Lo.end);
+        if (f.factor_qs()) {
+            ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
+            return;
+        }
+    }
+    TiledFactor<T, false, 8, EQ> f(P, sm, Lo.end);
     ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
 }
 
@@ -108,8 +124,8 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunc
             else run_policy<T, StreamFactor<T, false, UNIT>>(P, sm, L);
         } else if (ELIM && pol == kPolicyElim) {
             if constexpr (ELIM) {
-                if (P.p > 0) run_policy<T, ElimFactor<T, true>>(P, sm, L);
-                else run_policy<T, ElimFactor<T, false>>(P, sm, L);
+                if (P.p > 0) run_elim<T, true>(P, sm, L);
+                else run_elim<T, false>(P, sm, L);
             }
         } else if (pol == kPolicyGenericLds) {
             run_policy<T, GenericFactor<T, kFwdThreads, true>>(P, sm, L);
@@ -132,6 +148,14 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_uniform_kernel(FwdLaun
         F f(P, sm, Lo.end);
         ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
     }
+}
+
+// Uniform batch on the elimination order (EQ: equality rows).
+template <typename T, bool EQ>
+__global__ __launch_bounds__(kFwdThreads) void qp_forward_elim_kernel(FwdLaunch L) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    for (int idx = blockIdx.x; idx < L.count; idx += gridDim.x) run_elim<T, EQ>(fwd_problem<T>(L, idx), sm, L);
 }
 
 // Once per kernel (the flag is per instantiation, i.e. per kernel function).
@@ -186,9 +210,13 @@ hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
                              : launch_uniform_tiled<T, false>(pol, L, st);
         if (pol == kPolicyStream)
             return L.neq > 0 ? launch_uniform_stream<T, true>(L, st) : launch_uniform_stream<T, false>(L, st);
-        if (pol == kPolicyElim)
-            return L.neq > 0 ? launch_uniform<T, ElimFactor<T, true>>(L, st)
-                             : launch_uniform<T, ElimFactor<T, false>>(L, st);
+        if (pol == kPolicyElim) {
+            auto kern = L.neq > 0 ? qp_forward_elim_kernel<T, true> : qp_forward_elim_kernel<T, false>;
+            if (L.neq > 0) set_lds_limit_once<qp_forward_elim_kernel<T, true>>(L.lds_limit);
+            else set_lds_limit_once<qp_forward_elim_kernel<T, false>>(L.lds_limit);
+            hipLaunchKernelGGL(kern, dim3(L.count), dim3(kFwdThreads), L.lds_bytes, st, L);
+            return hipGetLastError();
+        }
         if (pol == kPolicyGenericLds) return launch_uniform<T, GenericFactor<T, kFwdThreads, true>>(L, st);
         return launch_uniform<T, GenericFactor<T, kFwdThreads, false>>(L, st);
     }

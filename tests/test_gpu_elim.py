@@ -2,8 +2,8 @@
 on the LU of K_sym) on the GPU against the FP64 oracle: z, s, lambda, nu and
 every gradient of every problem, at nineq < nz, nineq = nz, with and without
 equality rows, with no inequality rows, and with ragged sizes that end in a
-partial 16x16 tile.  The variant factors Qs once per solve, so a Q that is not
-positive definite must end BREAKDOWN with zero gradients."""
+partial 16x16 tile.  The variant factors Qs once per solve; where Qs is not
+positive definite the problem is solved by the tiled policy."""
 import numpy as np
 import pytest
 
@@ -85,19 +85,32 @@ def test_elimination_order_paper_scale_every_problem():
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_elimination_order_needs_positive_definite_q(dtype):
-    """Q = 0 in one problem: Qs cannot be factored, so that problem ends
-    BREAKDOWN with zero gradients; the other problems of the batch are
-    unaffected."""
-    assert __import__("paper_1703_00443_amd.binding", fromlist=["plan"]).plan(
-        __import__("torch").float64, 40, 20, 0, ELIM)[0] == ELIM
-    b = synth.make_batch(seed=77, B=4, n=40, m=20, p=0)
-    b.Q[1] = 0.0
+def test_elimination_order_falls_back_where_q_is_not_definite(dtype):
+    """Qs not positive definite (a zero block: the variables 20..39 enter the
+    objective only linearly): Qs cannot be factored, and the kernel solves the
+    problem with the tiled policy instead.  G = [I; -1^T], h = [u; 10] bounds
+    every variable (z <= u, sum z >= -10), so the problems stay bounded.  Every
+    problem of the batch (two with the zero block) against the oracle replay,
+    z also against the tiled variant."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from parity import TOL_Z, z_err
+    n = 40
+    assert qb.plan(torch.float64, n, n + 1, 0, ELIM)[0] == ELIM
+    base = synth.make_batch(seed=77, B=4, n=n, m=0, p=0)
+    rng = np.random.default_rng(78)
+    G = np.broadcast_to(np.vstack([np.eye(n), -np.ones((1, n))]), (4, n + 1, n)).copy()
+    h = np.hstack([rng.uniform(0.5, 1.5, (4, n)), np.full((4, 1), 10.0)])
+    b = synth.QPBatch(base.Q.copy(), base.q, base.A, base.b, G, h, base.g)
+    for i in (1, 2):
+        b.Q[i, 20:, :] = 0.0
+        b.Q[i, :, 20:] = 0.0
     out = _run(b, dtype)
-    assert int(out["status"][1]) == 2
-    for k in ("dQ", "dq", "dG", "dh"):
-        assert np.all(out[k][1] == 0), k
-    assert all(int(out["status"][i]) == 0 for i in (0, 2, 3))
+    tiled = _run(b, dtype, variant=3, need_grad=False)
+    _check_all(b, out, dtype, "elim_semidefinite_%s" % np.dtype(dtype).name)
+    for i in range(4):
+        if out["iters"][i] == tiled["iters"][i]:
+            assert z_err(out["z"][i], tiled["z"][i]) <= TOL_Z[dtype]
 
 
 def test_elimination_order_plan_falls_back():
