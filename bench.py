@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QP solves/s fwd+bwd (B=128,n=m=100) vs plain; p50/p99 latency in serving"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X published dense peaks (vector = matrix)
 HBM_GBS = 8000.0
-KERNEL_SOURCES = ("qp_core.hpp", "qp_ipm.hpp", "qp_policies.hpp", "qp_stream.hpp", "qp_forward.hpp", "qp_forward.hip",
+KERNEL_SOURCES = ("qp_core.hpp", "qp_ipm.hpp", "qp_policies.hpp", "qp_stream.hpp", "qp_elim.hpp", "qp_forward.hpp", "qp_forward.hip",
                   "qp_forward_f32.hip", "qp_forward_f64.hip")
 
 

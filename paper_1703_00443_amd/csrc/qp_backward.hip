@@ -279,7 +279,10 @@ __device__ void bwd_solve_mixed(const BProb<float> &P, unsigned char *smem, int 
     __syncthreads();
 }
 
-template <typename T, int NT>
+// WP: refinement in the working precision (FP64; FP32 with QP_FLAG_BWD_FP32).
+// The two FP32 schemes are separate instantiations: carrying both in one
+// kernel raised the default one from 154 registers to 256 with spills.
+template <typename T, int NT, bool WP>
 __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
@@ -291,18 +294,14 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
             for (int e = tid; e < P.n + P.m + P.p; e += NT) P.adj[e] = T(0);
             continue;
         }
-        bool mixed = false;
-        if constexpr (sizeof(T) == 4) mixed = (L.flags & QP_FLAG_BWD_FP32) == 0;
-        if (mixed) {
-            if constexpr (sizeof(T) == 4) {
-                const int stage = bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit);
-                if (stage == 2)
-                    bwd_solve_mixed<NT, 2>(P, smem_raw, L.refine_steps);
-                else if (stage == 1)
-                    bwd_solve_mixed<NT, 1>(P, smem_raw, L.refine_steps);
-                else
-                    bwd_solve_mixed<NT, 0>(P, smem_raw, L.refine_steps);
-            }
+        if constexpr (!WP && sizeof(T) == 4) {
+            const int stage = bwd_mixed_stage(P.n, P.m, P.p, L.lds_limit);
+            if (stage == 2)
+                bwd_solve_mixed<NT, 2>(P, smem_raw, L.refine_steps);
+            else if (stage == 1)
+                bwd_solve_mixed<NT, 1>(P, smem_raw, L.refine_steps);
+            else
+                bwd_solve_mixed<NT, 0>(P, smem_raw, L.refine_steps);
         } else {
         const int n = P.n, m = P.m, p = P.p;
         const BwdLayout Lo(n, m, p);
@@ -467,11 +466,15 @@ constexpr int kBwdThreads = 512;
 template <typename T>
 static hipError_t launch_bwd_t(const BwdLaunch &L, hipStream_t st, int max_rows) {
     if (L.count <= 0) return hipSuccess;
-    auto k1 = qp_backward_solve_kernel<T, kBwdThreads>;
-    static bool attr_done = false;
-    if (!attr_done) {
+    // FP64 always refines in its own precision; FP32 does with QP_FLAG_BWD_FP32
+    const bool wp = sizeof(T) == 8 || (L.flags & QP_FLAG_BWD_FP32) != 0;
+    auto k1 = qp_backward_solve_kernel<T, kBwdThreads, true>;
+    if constexpr (sizeof(T) == 4)
+        if (!wp) k1 = qp_backward_solve_kernel<T, kBwdThreads, false>;
+    static bool attr_done[2] = {false, false};
+    if (!attr_done[wp]) {
         (void)hipFuncSetAttribute((const void *)k1, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
-        attr_done = true;
+        attr_done[wp] = true;
     }
     hipLaunchKernelGGL(k1, dim3(L.count), dim3(kBwdThreads), L.lds_bytes, st, L);
     hipError_t e = hipGetLastError();
