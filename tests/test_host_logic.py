@@ -71,13 +71,19 @@ def test_autotune_buckets_and_lookup(tmp_path):
 
 
 def test_committed_table_is_valid():
+    """Keys are eq/noeq, optionally with a nineq/nz class; the elimination order
+    (5) appears only in the classes with nineq <= nz and buckets of nz <= 128."""
     t = AutotuneTable.load()
+    classes = ("r0", "r1", "r2")
     for dk, per in t.data.items():
         assert dk in ("f32", "f64")
-        for eq, buckets in per.items():
-            assert eq in ("eq", "noeq")
+        for key, buckets in per.items():
+            eq, _, rc = key.partition("/")
+            assert eq in ("eq", "noeq") and rc in ("",) + classes, key
             for b, v in buckets.items():
-                assert 0 <= int(b) < len(BUCKETS) and v in (1, 2, 3, 4)
+                assert 0 <= int(b) < len(BUCKETS) and v in (1, 2, 3, 4, 5)
+                if v == 5:
+                    assert rc in classes and BUCKETS[int(b)][1] <= 128, (key, b)
 
 
 def test_algorithmic_flops_counts():
