@@ -34,6 +34,8 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X published dense peaks (vect
 HBM_GBS = 8000.0
 KERNEL_SOURCES = ("qp_core.hpp", "qp_ipm.hpp", "qp_policies.hpp", "qp_stream.hpp", "qp_elim.hpp", "qp_forward.hpp", "qp_forward.hip",
                   "qp_forward_f32.hip", "qp_forward_f64.hip")
+# (the elimination-order and uneven-batch units only instantiate launchers of
+# qp_forward.hpp; the paper-scale kernel lives in qp_forward_{f32,f64}.hip)
 
 
 def algorithmic_flops(n, m, p, iters, final_factor=True):

@@ -199,10 +199,29 @@ static hipError_t launch_uniform_stream(const FwdLaunch &L, hipStream_t st) {
 
 __global__ void qp_zero_counter_kernel(int *c);
 
+// Each launcher is instantiated in a translation unit of its own per element
+// type (qp_forward_{f32,f64}.hip, qp_forward_elim_*.hip, qp_forward_varlen_*.hip)
+// so that the kernels compile in parallel.
 template <typename T>
-hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
+hipError_t launch_elim_t(const FwdLaunch &L, hipStream_t st) {
+    auto kern = L.neq > 0 ? qp_forward_elim_kernel<T, true> : qp_forward_elim_kernel<T, false>;
+    if (L.neq > 0) set_lds_limit_once<qp_forward_elim_kernel<T, true>>(L.lds_limit);
+    else set_lds_limit_once<qp_forward_elim_kernel<T, false>>(L.lds_limit);
+    hipLaunchKernelGGL(kern, dim3(L.count), dim3(kFwdThreads), L.lds_bytes, st, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_uniform_t(const FwdLaunch &L, hipStream_t st);
+
+template <typename T>
+hipError_t launch_varlen_t(const FwdLaunch &L, hipStream_t st);
+
+// Uniform batch: one kernel per policy (the elimination order's in its own unit).
+template <typename T>
+hipError_t launch_uniform_t(const FwdLaunch &L, hipStream_t st) {
     if (L.count <= 0) return hipSuccess;
-    if (L.desc == nullptr) {
+    {
         int bytes = 0;
         const int pol = plan_policy(sizeof(T), L.nz, L.nineq, L.neq, L.variant, L.lds_limit, &bytes);
         if (pol == kPolicyTiledGLds || pol == kPolicyTiledGGlobal || pol == kPolicyTiledBig)
@@ -210,16 +229,16 @@ hipError_t launch_fwd_t(const FwdLaunch &L, hipStream_t st) {
                              : launch_uniform_tiled<T, false>(pol, L, st);
         if (pol == kPolicyStream)
             return L.neq > 0 ? launch_uniform_stream<T, true>(L, st) : launch_uniform_stream<T, false>(L, st);
-        if (pol == kPolicyElim) {
-            auto kern = L.neq > 0 ? qp_forward_elim_kernel<T, true> : qp_forward_elim_kernel<T, false>;
-            if (L.neq > 0) set_lds_limit_once<qp_forward_elim_kernel<T, true>>(L.lds_limit);
-            else set_lds_limit_once<qp_forward_elim_kernel<T, false>>(L.lds_limit);
-            hipLaunchKernelGGL(kern, dim3(L.count), dim3(kFwdThreads), L.lds_bytes, st, L);
-            return hipGetLastError();
-        }
+        if (pol == kPolicyElim) return launch_elim_t<T>(L, st);
         if (pol == kPolicyGenericLds) return launch_uniform<T, GenericFactor<T, kFwdThreads, true>>(L, st);
         return launch_uniform<T, GenericFactor<T, kFwdThreads, false>>(L, st);
     }
+}
+
+// Uneven batch: the persistent kernel (instantiation by the call's needs).
+template <typename T>
+hipError_t launch_varlen_t(const FwdLaunch &L, hipStream_t st) {
+    if (L.count <= 0) return hipSuccess;
     const bool unit = !L.with_elim && (L.flags & QP_FLAG_G_UNIT_ROWS) != 0;
     auto kern = L.with_elim ? qp_forward_varlen_kernel<T, true, false>
                             : unit ? qp_forward_varlen_kernel<T, false, true> : qp_forward_varlen_kernel<T, false, false>;

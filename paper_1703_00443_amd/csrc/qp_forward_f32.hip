@@ -1,7 +1,8 @@
-// Forward kernels instantiated for float (one translation unit per element type).
+// Uniform-batch forward kernels instantiated for float (one translation unit per
+// element type and kernel family, compiled in parallel).
 #include "qp_forward.hpp"
 
 namespace qpmi {
-template hipError_t launch_fwd_t<float>(const FwdLaunch &, hipStream_t);
-template int resident_t<float>(int, bool);
+extern template hipError_t launch_elim_t<float>(const FwdLaunch &, hipStream_t);
+template hipError_t launch_uniform_t<float>(const FwdLaunch &, hipStream_t);
 }  // namespace qpmi

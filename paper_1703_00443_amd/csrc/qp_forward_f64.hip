@@ -1,7 +1,8 @@
-// Forward kernels instantiated for double (one translation unit per element type).
+// Uniform-batch forward kernels instantiated for double (one translation unit per
+// element type and kernel family, compiled in parallel).
 #include "qp_forward.hpp"
 
 namespace qpmi {
-template hipError_t launch_fwd_t<double>(const FwdLaunch &, hipStream_t);
-template int resident_t<double>(int, bool);
+extern template hipError_t launch_elim_t<double>(const FwdLaunch &, hipStream_t);
+template hipError_t launch_uniform_t<double>(const FwdLaunch &, hipStream_t);
 }  // namespace qpmi
