@@ -126,9 +126,11 @@ enum {
                                matrix C + D(s / lambda), C = G M G^T with M the inverse of
                                [Qs A^T; A 0] restricted to z, factored per Newton step.
                                Where Qs is not positive definite the problem is solved
-                               by the register-tile policy.  Applies for nz <= 128,
-                               nineq <= nz rounded up to a multiple of 16, and
-                               its LDS regions (G U_Q among them) fitting; elsewhere the
+                               by the tiled (or, above nz = 128, streamed) policy.
+                               Applies for nineq <= 128 and <= nz rounded up to a
+                               multiple of 16, with its LDS regions (G U_Q among them)
+                               fitting; the nz x nz factorizations run on register tiles
+                               up to nz = 128 and on streamed tiles above; elsewhere the
                                automatic plan runs.  Cheaper per step than forming H where
                                nineq < nz.  The forward ends by factoring H at the returned
                                iterate, so the state and the backward are those of the

@@ -6,7 +6,8 @@ the seeded generator, times forward + backward of every candidate variant
 (register-resident MFMA tiles where they apply, streamed MFMA tiles,
 LDS-resident generic, global-memory generic, and the paper's elimination order
 of Section 3.1.1 where nineq fits it) as one uneven launch and keeps the
-fastest one whose results are all usable.  The table is a JSON file; the
+fastest one whose results are all usable (no more problems short of OPTIMAL
+than under the automatic plan).  The table is a JSON file; the
 variant of a problem depends only on its own dims, so results do not depend on
 what else shares a launch.  Entries without a ratio class (key "eq" / "noeq")
 serve every class that has no entry of its own.
@@ -81,11 +82,12 @@ class AutotuneTable:
 def candidates(n: int, dtype: str, m: int = None):
     """Variants that apply to problems of up to n variables (and m inequality
     rows): generic, LDS, streamed tiles, the register-resident tiles (n <= 128;
-    FP32 n <= 256), and the elimination order (n <= 128, m <= n rounded up to 16)."""
+    FP32 n <= 256), and the elimination order (m <= 128 and m <= n rounded up
+    to 16; whether its LDS regions fit is the plan's to say)."""
     c = [1, 2, 4]
     if n <= 128 or (dtype == "f32" and n <= 256):
         c.append(3)
-    if m is not None and n <= 128 and m <= (n + 15) // 16 * 16:
+    if m is not None and m <= 128 and m <= (n + 15) // 16 * 16:
         c.append(5)
     return c
 
@@ -122,17 +124,24 @@ def tune(dtype="f32", samples: int = 24, seed: int = 7, reps: int = 3, buckets=N
             best = None
             key = eq if rc == "r3" else eq + "/" + rc
             cands = candidates(max(d[0] for d in dims), dk)
-            if all(5 in candidates(d[0], dk, d[1]) for d in dims):
+            from . import binding as qb
+            if all(5 in candidates(d[0], dk, d[1]) and qb.plan(tdt, d[0], d[1], d[2], 5)[0] == 5
+                   for d in dims):
                 cands = cands + [5]
-            for v in cands:
+            base_not_optimal = None
+            for v in [0] + cands:
                 vb = VarlenBatch(probs, dtype=tdt, variants=[v] * len(probs))
                 dl = vb.pack_vectors(g)
                 vb.forward(); vb.backward(dl)
                 torch.cuda.synchronize()
                 st = vb.status[:vb.count].cpu().numpy()
-                if not np.all((st == 0) | (st == 1) | (st == 4)):
-                    log("bucket %s %s variant %s: bad status %s" % (BUCKETS[bi], eq, VARIANT_NAMES[v],
-                                                                   np.bincount(st)))
+                if v == 0:
+                    # the automatic plan's outcome: no candidate may end fewer problems OPTIMAL
+                    base_not_optimal = int(np.sum(st != 0))
+                    continue
+                if not np.all((st == 0) | (st == 1) | (st == 4)) or int(np.sum(st != 0)) > base_not_optimal:
+                    log("bucket %s %s variant %s: statuses %s" % (BUCKETS[bi], key, VARIANT_NAMES[v],
+                                                                 np.bincount(st, minlength=5)))
                     continue
                 ts = []
                 for _ in range(reps):

@@ -84,7 +84,8 @@ int32_t qp_plan(qp_dtype dtype, qp_dims d, int32_t variant, int32_t *policy, int
         case kPolicyGenericGlobal: *policy = QP_VARIANT_GENERIC; break;
         case kPolicyGenericLds: *policy = QP_VARIANT_LDS; break;
         case kPolicyStream: *policy = QP_VARIANT_STREAM; break;
-        case kPolicyElim: *policy = QP_VARIANT_ELIM; break;
+        case kPolicyElim:
+        case kPolicyElimBig: *policy = QP_VARIANT_ELIM; break;
         default: *policy = QP_VARIANT_TILED; break;
     }
     if (lds_bytes) *lds_bytes = lds;
@@ -308,7 +309,7 @@ int32_t qp_forward_varlen(qp_dtype dtype, int32_t count, const qp_problem_desc *
         int l = 0;
         const int pol = fwd_plan(esz, d.nz, d.nineq, d.neq, var, lim, &l);
         if (pol == kPolicyNone) return QP_ETOOBIG;
-        with_elim |= pol == kPolicyElim;
+        with_elim |= pol == kPolicyElim || pol == kPolicyElimBig;
         lds = std::max(lds, l);
     }
     FwdLaunch L;

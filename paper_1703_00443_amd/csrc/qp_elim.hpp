@@ -29,7 +29,7 @@
 // keep (H at the returned iterate): it is formed and factored once more in
 // finish(), so the backward is shared.
 #pragma once
-#include "qp_policies.hpp"
+#include "qp_stream.hpp"
 
 namespace qpmi {
 
@@ -58,8 +58,18 @@ struct ElimLayout {
     }
 };
 
-__host__ __device__ inline int elim_lds_elems(int base, int n, int m, int p) {
-    const int a = ElimLayout(base, n, m, p).end, b = TiledLayout<false>(base, n, m, p).end;
+// LDS elements of the policy: its own regions, and those of the nz x nz
+// factorizations (the tiled layout, or BIG: the streamed one), whichever is larger;
+// 0 when the streamed layout does not fit (BIG).
+__host__ __device__ inline int elim_lds_elems(int esz, int base, int n, int m, int p, bool big, int lds_limit) {
+    const int a = ElimLayout(base, n, m, p).end;
+    int b = TiledLayout<false>(base, n, m, p).end;
+    if (big) {
+        int kc = 4;
+        bool s_lds = true;
+        if (!stream_plan(esz, base, n, m, p, lds_limit, &kc, &s_lds)) return 0;
+        b = StreamLayout(base, n, m, p, kc, s_lds).end;
+    }
     return a > b ? a : b;
 }
 
@@ -94,8 +104,12 @@ __device__ __forceinline__ void tile_product(int rows, int cols, int kdim, bool 
 // One register-tile factor object serves all three factorizations (Qs once,
 // C + D^{-1} every Newton step, H at the end), re-aimed between the nz x nz
 // and the nineq x nineq sizes: separate objects for them kept three sets of
-// register tiles alive and spilled to scratch memory.
-template <typename T, bool EQ>
+// register tiles alive and spilled to scratch memory.  BIG (nz above the
+// register tiles' 128): Qs and H are factored by the streamed-tile policy in
+// the state buffer instead (objects local to factor_qs() and finish(), which
+// hold no registers between its calls), and the register-tile object is only
+// the nineq x nineq factor.
+template <typename T, bool EQ, bool BIG = false>
 struct ElimFactor {
     static constexpr int NT = 64 * kTiledWaves;
     // dz = U_Q (xi0 - Vh^T w) carries a rounding error of the size of
@@ -110,6 +124,8 @@ struct ElimFactor {
     // nineq x nineq system); solve_g returns D^{-1} w for G dz
     static constexpr bool kSolveGz = true;
     using TF = TiledFactor<T, false, 8, EQ, false>;
+    using SF = StreamFactor<T, EQ, false>;
+    Prob<T> Pr;  // BIG: the streamed factor objects are built from it
     T *sm;
     int base;
     int n, m, p, ldu, ldv, ldz;
@@ -120,7 +136,7 @@ struct ElimFactor {
     TF tf;  // nz x nz in factor_qs(), prepare() and finish(), nineq x nineq in between
 
     __device__ __forceinline__ ElimFactor(const Prob<T> &P, T *sm_, int base_)
-        : sm(sm_), base(base_), tf(P, sm_, base_) {
+        : Pr(P), sm(sm_), base(base_), tf(P, sm_, base_) {
         n = P.n; m = P.m; p = P.p;
         Q = P.Q; G = P.G;
         const StateLayout SL = state_layout(sizeof(T), n, m, p);
@@ -138,6 +154,21 @@ struct ElimFactor {
     // Once per solve, before the driver starts: U_Q, At and U_A into the
     // state.  False (uniformly) when Qs or A's Schur complement does not factor.
     __device__ __forceinline__ bool factor_qs() {
+        if constexpr (BIG) {
+            // the streamed policy factors in place in the state's U region
+            // (upper triangle: U_Q), with equality rows At and S_A too
+            SF qf(Pr, sm, base);
+            qf.m = 0;  // H = Qs: no rows of G
+            const bool ok = qf.factor(nullptr);
+            if constexpr (EQ)
+                if (ok && qf.s_lds)
+                    for (int e = threadIdx.x; e < p * p; e += NT) {
+                        const int i = e / p, j = e - i * p;
+                        US[e] = qf.S[i * qf.lds + j];
+                    }
+            __syncthreads();
+            return ok;
+        }
         tf.retarget(n, 0, p, sm, base);  // H = Qs: no rows of G
         tf.prepare();                     // no equality rows: Qs staged in the state's U region
         const bool ok = tf.factor(nullptr);  // with equality rows: U_Q, At and S_A too
@@ -331,6 +362,10 @@ struct ElimFactor {
     // factor can stay positive definite at iterates where H no longer is in
     // working precision; false then (the driver returns the previous iterate).
     __device__ __forceinline__ bool finish(const T *D) {
+        if constexpr (BIG) {
+            SF hf(Pr, sm, base);
+            return hf.factor(D) && hf.finish(D);
+        }
         tf.retarget(n, m, p, sm, base);
         tf.prepare();
         return tf.factor(D) && tf.finish(D);

@@ -19,11 +19,13 @@ constexpr int kFwdThreads = 64 * kTiledWaves;
 __host__ __device__ inline int plan_policy(int esz, int n, int m, int p, int variant, int lds_limit,
                                            int *lds_bytes) {
     const int base = IpmLayout(n, m, p).end;
-    if (variant == QP_VARIANT_ELIM && n <= kTiledMaxN && m <= u_ld(n)) {
+    if (variant == QP_VARIANT_ELIM && m <= u_ld(n) && m <= kTiledMaxN) {
         // taken on request (or from an autotune table); where it does not
-        // apply the automatic plan runs
-        const int el = elim_lds_elems(base, n, m, p) * esz;
-        if (el <= lds_limit) { *lds_bytes = el; return kPolicyElim; }
+        // apply the automatic plan runs.  Above the register tiles' nz the
+        // nz x nz factorizations run on the streamed policy (BIG).
+        const bool big = n > kTiledMaxN;
+        const int el = elim_lds_elems(esz, base, n, m, p, big, lds_limit) * esz;
+        if (el > 0 && el <= lds_limit) { *lds_bytes = el; return big ? kPolicyElimBig : kPolicyElim; }
     }
     if (variant == QP_VARIANT_AUTO || variant == QP_VARIANT_TILED || variant == QP_VARIANT_ELIM) {
         if (n <= kTiledMaxN) {
@@ -66,18 +68,23 @@ __device__ __forceinline__ void run_policy(const Prob<T> P, T *sm, const FwdLaun
 
 // The elimination order, or the tiled policy where Qs does not factor (the
 // decision is made before the solve, so each Newton loop is its own code).
-template <typename T, bool EQ>
+template <typename T, bool EQ, bool BIG>
 __device__ __forceinline__ void run_elim(const Prob<T> &P, T *sm, const FwdLaunch &L) {
     const IpmLayout Lo(P.n, P.m, P.p);
     {
-        ElimFactor<T, EQ> f(P, sm, Lo.end);
+        ElimFactor<T, EQ, BIG> f(P, sm, Lo.end);
         if (f.factor_qs()) {
             ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
             return;
         }
     }
-    TiledFactor<T, false, 8, EQ> f(P, sm, Lo.end);
-    ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
+    if constexpr (BIG) {
+        StreamFactor<T, EQ> f(P, sm, Lo.end);
+        ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
+    } else {
+        TiledFactor<T, false, 8, EQ> f(P, sm, Lo.end);
+        ipm_solve<T, kFwdThreads>(P, sm, Lo, f, L.max_iter, (T)L.tol, L.status, L.iters);
+    }
 }
 
 template <typename T, bool EQ, bool UNIT>
@@ -122,10 +129,15 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_varlen_kernel(FwdLaunc
         } else if (pol == kPolicyStream) {
             if (P.p > 0) run_policy<T, StreamFactor<T, true, UNIT>>(P, sm, L);
             else run_policy<T, StreamFactor<T, false, UNIT>>(P, sm, L);
-        } else if (ELIM && pol == kPolicyElim) {
+        } else if (ELIM && (pol == kPolicyElim || pol == kPolicyElimBig)) {
             if constexpr (ELIM) {
-                if (P.p > 0) run_elim<T, true>(P, sm, L);
-                else run_elim<T, false>(P, sm, L);
+                if (pol == kPolicyElimBig) {
+                    if (P.p > 0) run_elim<T, true, true>(P, sm, L);
+                    else run_elim<T, false, true>(P, sm, L);
+                } else {
+                    if (P.p > 0) run_elim<T, true, false>(P, sm, L);
+                    else run_elim<T, false, false>(P, sm, L);
+                }
             }
         } else if (pol == kPolicyGenericLds) {
             run_policy<T, GenericFactor<T, kFwdThreads, true>>(P, sm, L);
@@ -150,12 +162,14 @@ __global__ __launch_bounds__(kFwdThreads) void qp_forward_uniform_kernel(FwdLaun
     }
 }
 
-// Uniform batch on the elimination order (EQ: equality rows).
-template <typename T, bool EQ>
+// Uniform batch on the elimination order (EQ: equality rows; BIG: streamed
+// nz x nz factorizations).
+template <typename T, bool EQ, bool BIG>
 __global__ __launch_bounds__(kFwdThreads) void qp_forward_elim_kernel(FwdLaunch L) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
-    for (int idx = blockIdx.x; idx < L.count; idx += gridDim.x) run_elim<T, EQ>(fwd_problem<T>(L, idx), sm, L);
+    for (int idx = blockIdx.x; idx < L.count; idx += gridDim.x)
+        run_elim<T, EQ, BIG>(fwd_problem<T>(L, idx), sm, L);
 }
 
 // Once per kernel (the flag is per instantiation, i.e. per kernel function).
@@ -202,13 +216,18 @@ __global__ void qp_zero_counter_kernel(int *c);
 // Each launcher is instantiated in a translation unit of its own per element
 // type (qp_forward_{f32,f64}.hip, qp_forward_elim_*.hip, qp_forward_varlen_*.hip)
 // so that the kernels compile in parallel.
-template <typename T>
-hipError_t launch_elim_t(const FwdLaunch &L, hipStream_t st) {
-    auto kern = L.neq > 0 ? qp_forward_elim_kernel<T, true> : qp_forward_elim_kernel<T, false>;
-    if (L.neq > 0) set_lds_limit_once<qp_forward_elim_kernel<T, true>>(L.lds_limit);
-    else set_lds_limit_once<qp_forward_elim_kernel<T, false>>(L.lds_limit);
+template <typename T, bool BIG>
+static hipError_t launch_elim_k(const FwdLaunch &L, hipStream_t st) {
+    auto kern = L.neq > 0 ? qp_forward_elim_kernel<T, true, BIG> : qp_forward_elim_kernel<T, false, BIG>;
+    if (L.neq > 0) set_lds_limit_once<qp_forward_elim_kernel<T, true, BIG>>(L.lds_limit);
+    else set_lds_limit_once<qp_forward_elim_kernel<T, false, BIG>>(L.lds_limit);
     hipLaunchKernelGGL(kern, dim3(L.count), dim3(kFwdThreads), L.lds_bytes, st, L);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_elim_t(const FwdLaunch &L, hipStream_t st, int big) {
+    return big ? launch_elim_k<T, true>(L, st) : launch_elim_k<T, false>(L, st);
 }
 
 template <typename T>
@@ -229,7 +248,7 @@ hipError_t launch_uniform_t(const FwdLaunch &L, hipStream_t st) {
                              : launch_uniform_tiled<T, false>(pol, L, st);
         if (pol == kPolicyStream)
             return L.neq > 0 ? launch_uniform_stream<T, true>(L, st) : launch_uniform_stream<T, false>(L, st);
-        if (pol == kPolicyElim) return launch_elim_t<T>(L, st);
+        if (pol == kPolicyElim || pol == kPolicyElimBig) return launch_elim_t<T>(L, st, pol == kPolicyElimBig);
         if (pol == kPolicyGenericLds) return launch_uniform<T, GenericFactor<T, kFwdThreads, true>>(L, st);
         return launch_uniform<T, GenericFactor<T, kFwdThreads, false>>(L, st);
     }

@@ -2,5 +2,5 @@
 #include "qp_forward.hpp"
 
 namespace qpmi {
-template hipError_t launch_elim_t<float>(const FwdLaunch &, hipStream_t);
+template hipError_t launch_elim_t<float>(const FwdLaunch &, hipStream_t, int);
 }  // namespace qpmi

@@ -3,6 +3,6 @@
 #include "qp_forward.hpp"
 
 namespace qpmi {
-extern template hipError_t launch_elim_t<double>(const FwdLaunch &, hipStream_t);
+extern template hipError_t launch_elim_t<double>(const FwdLaunch &, hipStream_t, int);
 template hipError_t launch_uniform_t<double>(const FwdLaunch &, hipStream_t);
 }  // namespace qpmi

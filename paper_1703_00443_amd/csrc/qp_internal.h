@@ -100,7 +100,7 @@ struct BwdLaunch {
 // requested variant and the device LDS limit, so a problem is solved with the
 // same arithmetic alone or inside any batch.
 enum { kPolicyGenericGlobal = 0, kPolicyGenericLds = 1, kPolicyTiledGGlobal = 2, kPolicyTiledGLds = 3,
-       kPolicyTiledBig = 4, kPolicyStream = 5, kPolicyElim = 6, kPolicyNone = -1 };
+       kPolicyTiledBig = 4, kPolicyStream = 5, kPolicyElim = 6, kPolicyElimBig = 7, kPolicyNone = -1 };
 int fwd_plan(int esz, int n, int m, int p, int variant, int lds_limit, int *lds_bytes);
 
 // Workgroups of the forward kernel that fit on the device at once with this LDS.
