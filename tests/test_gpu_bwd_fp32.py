@@ -73,3 +73,32 @@ def test_fp32_only_backward(case):
     # FP32 arithmetic against an FP64 reference at the same iterate
     assert np.median(errs) <= 5e-3, errs
     assert errs.max() <= 5e-2, errs
+
+
+def test_fp32_only_backward_uneven_batch_equals_uniform():
+    """QP_FLAG_BWD_FP32 through qp_backward_varlen: every problem's gradients
+    equal, to FP32 rounding, to the same problem's through qp_backward_batched
+    with the flag (the same per-problem code in another kernel), on problems of
+    several sizes."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    from paper_1703_00443_amd.varlen import VarlenBatch
+    dims = [(10, 20, 5), (40, 60, 0), (100, 100, 0), (64, 32, 8)]
+    probs = synth.make_varlen(31, dims, dtype=np.float32)
+    flag = qb.default_opts(torch.float32, flags=qb.FLAG_BWD_FP32)
+    vb = VarlenBatch(probs, dtype=torch.float32)
+    vb.forward(flag).backward(vb.pack_vectors([P["g"] for P in probs]), opts=flag)
+    torch.cuda.synchronize()
+    for i, P in enumerate(probs):
+        n, m, p = dims[i]
+        b = synth.QPBatch(*(np.asarray(P[k], np.float32)[None] if P.get(k) is not None else
+                            np.zeros((1, 0, n) if k in ("A", "G") else (1, 0), np.float32)
+                            for k in ("Q", "q", "A", "b", "G", "h", "g")))
+        one = _run(b, qb.FLAG_BWD_FP32)
+        r = vb.result(i)
+        assert r["iters"] == one["iters"][0]
+        np.testing.assert_allclose(r["z"], one["z"][0], rtol=1e-5, atol=1e-5 * np.abs(one["z"][0]).max())
+        sc = max(np.abs(one[k][0]).max() for k in KEYS if one[k] is not None and one[k].size)
+        for k in KEYS:
+            if one[k] is not None and one[k].size:
+                np.testing.assert_allclose(r[k], one[k][0], rtol=0, atol=1e-4 * sc, err_msg="%d %s" % (i, k))
