@@ -39,9 +39,11 @@ namespace qpmi {
 // solve's vectors.  The factorizations of Qs (prepare) and of H (finish) use
 // the n x n tiled layout from the same base: both run while none of these
 // regions is live.
+// With `uq`, a copy of U_Q (upper triangle read, ld u_ld(nz)) follows, for the
+// two triangular products of every solve.
 struct ElimLayout {
-    int vh, ldv, zz, ldz, cdg, dinv, u, xi, tn3, nu0, g1, wv, t1, t2, scr, end;
-    __host__ __device__ ElimLayout(int base, int n, int m, int p) {
+    int vh, ldv, zz, ldz, cdg, dinv, u, xi, tn3, nu0, g1, wv, t1, t2, scr, uq, end;
+    __host__ __device__ ElimLayout(int base, int n, int m, int p, bool with_uq) {
         // the nineq x nineq factor is seeded, never formed: its G staging
         // region (the end of its layout) is not used, and Vh starts there
         const TiledLayout<false> Ls(base, m, 0, 0);
@@ -54,6 +56,7 @@ struct ElimLayout {
         u = o; o += N; xi = o; o += N; tn3 = o; o += N;
         nu0 = o; o += Pp; g1 = o; o += M; wv = o; o += M; t1 = o; o += Pp; t2 = o; o += Pp;
         scr = o; o += 64 * kTiledWaves;
+        uq = o; o += with_uq ? n * u_ld(n) : 0;
         end = o;
     }
 };
@@ -61,8 +64,16 @@ struct ElimLayout {
 // LDS elements of the policy: its own regions, and those of the nz x nz
 // factorizations (the tiled layout, or BIG: the streamed one), whichever is larger;
 // 0 when the streamed layout does not fit (BIG).
+// Whether U_Q is copied to LDS: up to nz = 128, where the policy's regions
+// with the copy still fit (a function of the dims and the LDS size only).
+__host__ __device__ inline bool elim_uq_in_lds(int esz, int base, int n, int m, int p, int lds_limit) {
+    if (n > kTiledMaxN) return false;
+    const int a = ElimLayout(base, n, m, p, true).end, b = TiledLayout<false>(base, n, m, p).end;
+    return (a > b ? a : b) * esz <= lds_limit;
+}
+
 __host__ __device__ inline int elim_lds_elems(int esz, int base, int n, int m, int p, bool big, int lds_limit) {
-    const int a = ElimLayout(base, n, m, p).end;
+    const int a = ElimLayout(base, n, m, p, !big && elim_uq_in_lds(esz, base, n, m, p, lds_limit)).end;
     int b = TiledLayout<false>(base, n, m, p).end;
     if (big) {
         int kc = 4;
@@ -132,6 +143,8 @@ struct ElimFactor {
     const T *Q, *G;
     T *Ust, *Wt, *US;
     T *vh, *zz, *cdg, *dinv, *u, *xi, *tn3, *nu0, *g1, *wv, *t1, *t2, *scr;
+    T *Uq;          // U_Q for the solves: the LDS copy where it fits, else the state's U region
+    bool uq_lds;
     const T *Dcur;  // the scaling of the last factor() call
     TF tf;  // nz x nz in factor_qs(), prepare() and finish(), nineq x nineq in between
 
@@ -144,7 +157,9 @@ struct ElimFactor {
         Wt = (T *)(P.state + SL.off_Wt);
         US = (T *)(P.state + SL.off_US);
         ldu = u_ld(n);
-        const ElimLayout L(base, n, m, p);
+        uq_lds = !BIG && elim_uq_in_lds(sizeof(T), base, n, m, p, P.lds_limit);
+        const ElimLayout L(base, n, m, p, uq_lds);
+        Uq = uq_lds ? sm + L.uq : Ust;
         ldv = L.ldv; ldz = L.ldz;
         vh = sm + L.vh; zz = sm + L.zz; cdg = sm + L.cdg; dinv = sm + L.dinv;
         u = sm + L.u; xi = sm + L.xi; tn3 = sm + L.tn3; nu0 = sm + L.nu0; g1 = sm + L.g1;
@@ -188,6 +203,14 @@ struct ElimFactor {
     // The driver's once-per-solve step: Vh and Z into LDS; C below U_Q in the
     // state and its diagonal in LDS.
     __device__ __forceinline__ void prepare() {
+        if (uq_lds) {
+            // the upper triangle only: C is about to go below it in the state
+            for (int e = threadIdx.x; e < n * ldu; e += NT) {
+                const int i = e / ldu, j = e - i * ldu;
+                if (j >= i && j < n) Uq[e] = Ust[e];
+            }
+            __syncthreads();
+        }
         if (m == 0) return;
         const T *Gp = G, *Up = Ust;
         T *vp = vh;
@@ -287,7 +310,7 @@ struct ElimFactor {
     }
 
     __device__ __forceinline__ void solve(const T *f, const T *r4, T *dz, T *dnu) {
-        ut_mv_split<T, NT>(Ust, ldu, n, f, u, scr);  // u = U_Q^T f
+        ut_mv_split<T, NT>(Uq, ldu, n, f, u, scr);  // u = U_Q^T f
         const T *x0 = u;
         if constexpr (EQ) {
             mv_rows<T, NT>(Wt, n, p, n, u, t1);
@@ -331,7 +354,7 @@ struct ElimFactor {
             for (int j = threadIdx.x; j < p; j += NT) dnu[j] = nu0[j];
             __syncthreads();
         }
-        u_mv<T, NT>(Ust, ldu, n, x0, dz);  // dz = U_Q xi
+        u_mv<T, NT>(Uq, ldu, n, x0, dz);  // dz = U_Q xi
         __syncthreads();
     }
 
