@@ -134,6 +134,7 @@ struct ElimFactor {
     // the solve yields w = D G dz directly (the paper's unknown in the
     // nineq x nineq system); solve_g returns D^{-1} w for G dz
     static constexpr bool kSolveGz = true;
+    static constexpr bool kFormResidual = false;
     using TF = TiledFactor<T, false, 8, EQ, false>;
     using SF = StreamFactor<T, EQ, false>;
     Prob<T> Pr;  // BIG: the streamed factor objects are built from it

@@ -20,6 +20,10 @@
 //   static constexpr bool kRefineAlways        refine every combined direction
 //   static constexpr bool kSolveGz             solve_g(f, r4, dz, dnu, gz) also
 //                                              returns G dz (see solve_gz)
+//   static constexpr bool kFormResidual        factor_res(D, z, lam, gz, gtl)
+//                                              factors as factor(D) and returns
+//                                              G z and G^T lam from the rows of G
+//                                              the formation of H reads
 //   bool finish(D)                             write the factor of [H A^T; A 0]
 //                                              at D to the state (false: none)
 #pragma once
@@ -222,10 +226,20 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
 
     // ---- Newton loop
     for (it = 0;; ++it) {
-        // residuals: rx = -(Qs z + q + G^T lam + A^T nu), rz = -(G z + s - h), ry = -(A z - b)
+        // residuals: rx = -(Qs z + q + G^T lam + A^T nu), rz = -(G z + s - h), ry = -(A z - b).
+        // Where G is streamed (F::kFormResidual), H is formed and factored
+        // first, at D = lam / s, and G z and G^T lam come from the same reads
+        // of G; the stop test and the status logic below are unchanged.
+        bool ok_res = true;
+        if constexpr (F::kFormResidual) {
+            for (int k = tid; k < m; k += NT) D[k] = lam[k] / s[k];
+            __syncthreads();
+            ok_res = fac.factor_res(D, z, lam, tm, rx);
+        } else {
+            fac.g_mv(z, tm);
+            fac.gt_mv(lam, rx);
+        }
         fac.qs_mv(z, tn);
-        fac.g_mv(z, tm);
-        fac.gt_mv(lam, rx);
         if (p > 0) {
             mv_rows<T, NT>(A, n, p, n, z, ry);  // A z
             mv_cols<T, NT>(A, n, p, n, nu, tn2);  // A^T nu
@@ -261,7 +275,9 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         const bool finite_now = vmin > T(0) && isfinite(mu);
 
         // factor at this iterate
-        const bool ok = finite_now && fac.factor(D);
+        bool ok;
+        if constexpr (F::kFormResidual) ok = finite_now && ok_res;
+        else ok = finite_now && fac.factor(D);
 
         if (!finite_now) { st = QP_STATUS_NONFINITE; break; }
         if (stalled) { st = ok ? QP_STATUS_STALLED : QP_STATUS_BREAKDOWN; break; }

@@ -78,6 +78,7 @@ template <typename T, int NT, bool HL>
 struct GenericFactor {
     static constexpr bool kRefineAlways = false;
     static constexpr bool kSolveGz = false;
+    static constexpr bool kFormResidual = false;
     int n, m, p;
     const T *Q, *G, *A;
     T *H;
@@ -363,6 +364,8 @@ struct TiledFactor {
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr bool kRefineAlways = false;
     static constexpr bool kSolveGz = false;
+    // G streamed in chunks: the residual's G z and G^T lam from the staged rows
+    static constexpr bool kFormResidual = !GL;
     static constexpr int NS = TileMap<NTL>::NS;
     using v4 = typename Mfma<T>::v4;
     int n, m, p, nt, np, pt, ldg, lds, ldu;
@@ -453,7 +456,15 @@ struct TiledFactor {
     // Accumulators start from Qs = (Q + Q^T) / 2 (identity on the padding); the
     // k loop runs outside the tile loop so that the MFMAs of the tiles of a
     // wavefront are independent and overlap their operand loads.
-    __device__ __forceinline__ void form(const T *D) {
+    // RES (G streamed in chunks): each staged chunk of rows also gives its
+    // entries of gz = G zr (16 lanes per row, as mv_rows) and its terms of
+    // gtl = G^T lr (one thread per column, n <= NT), so that the residual of
+    // the iterate needs no pass of its own over G.
+    template <bool RES = false>
+    __device__ __forceinline__ void form(const T *D, const T *zr = nullptr, const T *lr = nullptr,
+                                         T *gz = nullptr, T *gtl = nullptr) {
+        static_assert(!RES || (!GL && 16 * NTL <= NT), "column sums take one thread per column");
+        T cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;  // column threadIdx.x of G^T lr, rows k mod 4
         if (UNIT && unit) ur.diag(D, xv, n);  // G^T D G is diagonal
         lane_ids();
 #pragma unroll
@@ -487,6 +498,20 @@ struct TiledFactor {
                 __syncthreads();
                 lane_ids();
             }
+            if constexpr (RES) {
+                mv_rows<T, NT>(G, ldg, rows, n, zr, gz + k0);
+                const int i = threadIdx.x;
+                if (i < n) {
+                    int k = 0;
+                    for (; k + 3 < rows; k += 4) {
+                        cs0 += G[(size_t)k * ldg + i] * lr[k0 + k];
+                        cs1 += G[(size_t)(k + 1) * ldg + i] * lr[k0 + k + 1];
+                        cs2 += G[(size_t)(k + 2) * ldg + i] * lr[k0 + k + 2];
+                        cs3 += G[(size_t)(k + 3) * ldg + i] * lr[k0 + k + 3];
+                    }
+                    for (; k < rows; ++k) cs0 += G[(size_t)k * ldg + i] * lr[k0 + k];
+                }
+            }
             for (int kb = 0; kb < rows; kb += 4) {
                 const int k = kb + g;
                 const T *Gk = G + (size_t)k * ldg;
@@ -507,6 +532,8 @@ struct TiledFactor {
             for (int r = 0; r < 4; ++r)
                 if (Mfma<T>::row(g, r) < c) sq[s][r] = T(0);  // X part of the diagonal tile
         }
+        if constexpr (RES)
+            if ((int)threadIdx.x < n) gtl[threadIdx.x] = (cs0 + cs1) + (cs2 + cs3);
     }
 
     // The register tiles from a symmetric n x n matrix whose strict lower
@@ -718,6 +745,21 @@ struct TiledFactor {
 
     __device__ __forceinline__ bool factor(const T *D) {
         form(D);
+        if (!chol_inv()) return false;
+        if constexpr (EQ) return schur();
+        return true;
+    }
+
+    // factor(D), plus gz = G zr and gtl = G^T lr from the chunks of G that the
+    // formation stages (visible to every thread when it returns: chol_inv
+    // starts with a barrier)
+    __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, T *gz, T *gtl) {
+        if (UNIT && unit) {
+            g_mv(zr, gz);
+            gt_mv(lr, gtl);
+            return factor(D);
+        }
+        form<true>(D, zr, lr, gz, gtl);
         if (!chol_inv()) return false;
         if constexpr (EQ) return schur();
         return true;

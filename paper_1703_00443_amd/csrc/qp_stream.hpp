@@ -64,6 +64,7 @@ template <typename T, bool EQ, bool UNIT = false>
 struct StreamFactor {
     static constexpr bool kRefineAlways = false;
     static constexpr bool kSolveGz = false;
+    static constexpr bool kFormResidual = false;
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr int GT = 8;   // form(): tiles per wavefront and pass
     static constexpr int SE = sizeof(T) == 4 ? 32 : 16;  // form(): G elements staged per thread and chunk
