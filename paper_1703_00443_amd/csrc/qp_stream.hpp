@@ -64,7 +64,8 @@ template <typename T, bool EQ, bool UNIT = false>
 struct StreamFactor {
     static constexpr bool kRefineAlways = false;
     static constexpr bool kSolveGz = false;
-    static constexpr bool kFormResidual = false;
+    // the residual's G z and G^T lam from the rows of G the formation stages
+    static constexpr bool kFormResidual = true;
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr int GT = 8;   // form(): tiles per wavefront and pass
     static constexpr int SE = sizeof(T) == 4 ? 32 : 16;  // form(): G elements staged per thread and chunk
@@ -125,8 +126,16 @@ struct StreamFactor {
         J = t - i * (i + 1) / 2;
     }
 
-    __device__ __forceinline__ void form(const T *D) {
+    // RES: the first pass over the tiles also takes gz = G zr (16 lanes per
+    // row, as mv_rows) and gtl = G^T lr (accumulated in gtl by the thread that
+    // owns the column) from each staged chunk, so that the residual of the
+    // iterate needs no pass of its own over G.
+    template <bool RES = false>
+    __device__ __forceinline__ void form(const T *D, const T *zr = nullptr, const T *lr = nullptr,
+                                         T *gz = nullptr, T *gtl = nullptr) {
         if (UNIT && unit) ur.diag(D, xv, n);  // G^T D G is diagonal
+        if constexpr (RES)
+            for (int i = threadIdx.x; i < n; i += NT) gtl[i] = T(0);
         lane_ids();
         // upper tiles start at zero (they become X^T = L^{-T} strictly above the diagonal)
         for (int t = w; t < nt * nt; t += kTiledWaves) {
@@ -199,6 +208,23 @@ struct StreamFactor {
                 }
                 __syncthreads();
                 lane_ids();
+                if constexpr (RES) {
+                    if (t0 == 0) {
+                        mv_rows<T, NT>(gbuf, ldg, rows, n, zr, gz + k0);
+                        for (int i = threadIdx.x; i < n; i += NT) {
+                            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+                            int k = 0;
+                            for (; k + 3 < rows; k += 4) {
+                                a0 += gbuf[k * ldg + i] * lr[k0 + k];
+                                a1 += gbuf[(k + 1) * ldg + i] * lr[k0 + k + 1];
+                                a2 += gbuf[(k + 2) * ldg + i] * lr[k0 + k + 2];
+                                a3 += gbuf[(k + 3) * ldg + i] * lr[k0 + k + 3];
+                            }
+                            for (; k < rows; ++k) a0 += gbuf[k * ldg + i] * lr[k0 + k];
+                            gtl[i] += (a0 + a1) + (a2 + a3);
+                        }
+                    }
+                }
                 for (int kb = 0; kb < rows; kb += 4) {
                     const int k = kb + g;
                     const T *Gk = gbuf + k * ldg;
@@ -377,6 +403,20 @@ struct StreamFactor {
 
     __device__ __forceinline__ bool factor(const T *D) {
         form(D);
+        if (!chol_inv()) return false;
+        if constexpr (EQ) return schur();
+        return true;
+    }
+
+    // factor(D), plus gz = G zr and gtl = G^T lr from the chunks of G that the
+    // formation stages (form() ends with a barrier)
+    __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, T *gz, T *gtl) {
+        if (UNIT && unit) {
+            g_mv(zr, gz);
+            gt_mv(lr, gtl);
+            return factor(D);
+        }
+        form<true>(D, zr, lr, gz, gtl);
         if (!chol_inv()) return false;
         if constexpr (EQ) return schur();
         return true;
