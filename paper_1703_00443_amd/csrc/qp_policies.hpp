@@ -365,7 +365,8 @@ struct TiledFactor {
     static constexpr bool kRefineAlways = false;
     static constexpr bool kSolveGz = false;
     // G streamed in chunks: the residual's G z and G^T lam from the staged rows
-    static constexpr bool kFormResidual = !GL;
+    // (not in the unit-row instantiations, whose products are gathers)
+    static constexpr bool kFormResidual = !GL && !UNIT;
     static constexpr int NS = TileMap<NTL>::NS;
     using v4 = typename Mfma<T>::v4;
     int n, m, p, nt, np, pt, ldg, lds, ldu;
@@ -754,11 +755,7 @@ struct TiledFactor {
     // formation stages (visible to every thread when it returns: chol_inv
     // starts with a barrier)
     __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, T *gz, T *gtl) {
-        if (UNIT && unit) {
-            g_mv(zr, gz);
-            gt_mv(lr, gtl);
-            return factor(D);
-        }
+        static_assert(kFormResidual, "dense-G instantiations only");
         form<true>(D, zr, lr, gz, gtl);
         if (!chol_inv()) return false;
         if constexpr (EQ) return schur();

@@ -65,7 +65,8 @@ struct StreamFactor {
     static constexpr bool kRefineAlways = false;
     static constexpr bool kSolveGz = false;
     // the residual's G z and G^T lam from the rows of G the formation stages
-    static constexpr bool kFormResidual = true;
+    // (not in the unit-row instantiation, whose products are gathers)
+    static constexpr bool kFormResidual = !UNIT;
     static constexpr int NT = 64 * kTiledWaves;
     static constexpr int GT = 8;   // form(): tiles per wavefront and pass
     static constexpr int SE = sizeof(T) == 4 ? 32 : 16;  // form(): G elements staged per thread and chunk
@@ -411,11 +412,7 @@ struct StreamFactor {
     // factor(D), plus gz = G zr and gtl = G^T lr from the chunks of G that the
     // formation stages (form() ends with a barrier)
     __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, T *gz, T *gtl) {
-        if (UNIT && unit) {
-            g_mv(zr, gz);
-            gt_mv(lr, gtl);
-            return factor(D);
-        }
+        static_assert(kFormResidual, "dense-G instantiations only");
         form<true>(D, zr, lr, gz, gtl);
         if (!chol_inv()) return false;
         if constexpr (EQ) return schur();
