@@ -384,3 +384,26 @@ def test_fp64_tight_tolerance(tol):
         rs = P["G"] @ z + s - P["h"]
         err = max(float(s @ lam) / len(s), np.abs(rx).max(), np.abs(rs).max())
         assert err <= 10 * tol, (i, err)
+
+
+# G streamed through LDS: the residual's G z and G^T lam come from the chunks of
+# rows that the formation of H stages.  Row counts that end in a partial chunk,
+# and one that is not a multiple of 4, with and without equality rows, in the
+# register-tile policy (both tile grids) and the streamed-tile policy.
+STREAMED_G = [(np.float64, 100, 301, 5, 3), (np.float32, 200, 403, 0, 3), (np.float32, 120, 290, 7, 3),
+              (np.float64, 150, 157, 6, 4), (np.float32, 300, 45, 0, 4)]
+
+
+@pytest.mark.parametrize("dtype,n,m,p,variant", STREAMED_G)
+def test_residual_products_from_streamed_g(dtype, n, m, p, variant):
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    pol, lds = qb.plan(tdt, n, m, p, variant)
+    assert pol == variant, (pol, variant)
+    if variant == qb.VARIANT_TILED:  # the streamed policy always stages G in chunks
+        esz = np.dtype(dtype).itemsize
+        assert lds < m * (16 * ((n + 15) // 16) + 1) * esz, "G would be LDS-resident at %s" % ((n, m, p),)
+    b = synth.make_batch(seed=6100 + n + m + p, B=4, n=n, m=m, p=p)
+    out = _run(b, dtype, opts_over={"variant": variant})
+    _check(b, out, dtype, range(4), tag="streamed_g_%s%s" % (np.dtype(dtype).name, (n, m, p)))
