@@ -344,9 +344,8 @@ __global__ __launch_bounds__(NT) void qp_backward_solve_kernel(BwdLaunch L) {
         // left, the correction times rho, is below 1e-8 of the solution; a
         // correction larger than half the previous one (no longer converging)
         // is not applied.  Near the end of a solve H can be ill-conditioned
-        // enough that one step leaves an adjoint error of 1e-2.  Near the end of a solve H
-        // can be ill-conditioned enough that one step leaves an adjoint error
-        // of 1e-2 where several steps reach 1e-6 or better.
+        // enough that one step leaves an adjoint error of 1e-2 where several
+        // steps reach 1e-6 or better.
         T *red = sm + Lo.red;
         T prev_applied = pinf<T>();
         for (int r = 0; r < L.refine_steps; ++r) {
