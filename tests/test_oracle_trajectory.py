@@ -2,7 +2,7 @@
 
 GPU parity replays the oracle for the GPU's step count, so the oracle's
 iterates after k steps (not only its converged solution) decide every parity
-verdict.  These tests pin them:
+outcome.  These tests pin them:
 
 * hand-derived fixtures (tests/golden/trajectory/*.json, each with its written
   derivation): the initial point, and for the one-variable box QP every
