@@ -407,3 +407,36 @@ def test_residual_products_from_streamed_g(dtype, n, m, p, variant):
     b = synth.make_batch(seed=6100 + n + m + p, B=4, n=n, m=m, p=p)
     out = _run(b, dtype, opts_over={"variant": variant})
     _check(b, out, dtype, range(4), tag="streamed_g_%s%s" % (np.dtype(dtype).name, (n, m, p)))
+
+
+@pytest.mark.parametrize("dtype,n,m,variant", [(np.float64, 100, 301, 3), (np.float32, 200, 403, 3),
+                                               (np.float64, 150, 157, 4)])
+def test_status_codes_with_streamed_g(dtype, n, m, variant):
+    """Where G is streamed, each Newton step factors before its residual is
+    tested: a non-finite input still ends NONFINITE, a negative definite Q
+    BREAKDOWN, and the good problem of the batch is bitwise the same problem
+    solved alone, with zero gradients for the other two."""
+    import torch
+    from paper_1703_00443_amd import binding as qb
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    b = synth.make_batch(seed=77 + n, B=3, n=n, m=m, p=0)
+    Q, q = b.Q.copy(), b.q.copy()
+    q[1, 0] = np.nan             # problem 1: non-finite input
+    Q[2] = -1e4 * np.eye(n)      # problem 2: Q + G^T D G negative definite -> breakdown
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(dtype))).to(dev)
+    opts = qb.default_opts(tdt, variant=variant)
+    prob = qb.make_problem(T(Q), T(q), None, None, T(b.G), T(b.h))
+    fw = qb.forward(prob, opts)
+    gr = qb.backward(prob, fw, T(b.g), opts)
+    one = qb.make_problem(T(Q[:1]), T(q[:1]), None, None, T(b.G[:1]), T(b.h[:1]))
+    fw1 = qb.forward(one, opts)
+    gr1 = qb.backward(one, fw1, T(b.g[:1]), opts)
+    torch.cuda.synchronize()
+    st = fw.status.cpu().numpy()
+    assert st[0] in (0, 4) and st[1] == 3 and st[2] == 2, st
+    np.testing.assert_array_equal(fw.z[0].cpu().numpy(), fw1.z[0].cpu().numpy())
+    for k in ("dQ", "dq", "dG", "dh"):
+        g = getattr(gr, k).cpu().numpy()
+        assert np.all(g[1:] == 0), k
+        np.testing.assert_array_equal(g[0], getattr(gr1, k)[0].cpu().numpy(), err_msg=k)
