@@ -196,6 +196,38 @@ __device__ __forceinline__ void mv_rows(const T *__restrict__ M, int ld, int row
     }
 }
 
+// Rows [0, rows) of a staged chunk M (ld) that holds rows k0.. of G: the
+// row dots gz[k0 + r] = (G x)_r by the arithmetic of mv_rows, and each row's
+// weight in the affine right-hand side, wsc[k0 + r] = lam + D rz with
+// rz = -(gz + s - h) (the residual of the slack equation).  No barrier at the end.
+template <typename T, int NT>
+__device__ __forceinline__ void chunk_rows_res(const T *__restrict__ M, int ld, int k0, int rows, int cols,
+                                               const T *x, const T *lam, const T *D, const T *s,
+                                               const T *h, T *gz, T *wsc) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+    for (int r0 = 4 * w; r0 < rows; r0 += 4 * NW) {
+        const int r = r0 + g < rows ? r0 + g : rows - 1;
+        const T *row = M + (size_t)r * ld;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int c = cl;
+        for (; c + 48 < cols; c += 64) {
+            a0 += row[c] * x[c];
+            a1 += row[c + 16] * x[c + 16];
+            a2 += row[c + 32] * x[c + 32];
+            a3 += row[c + 48] * x[c + 48];
+        }
+        for (; c < cols; c += 16) a0 += row[c] * x[c];
+        const T dot = row16_sum((a0 + a1) + (a2 + a3));
+        if (cl == 0 && r0 + g < rows) {
+            const int k = k0 + r0 + g;
+            gz[k] = dot;
+            const T rz = -(dot + s[k] - h[k]);
+            wsc[k] = lam[k] + D[k] * rz;
+        }
+    }
+}
+
 // The largest row 1-norm max_r sum_{c<cols} |M[r][c]|, returned to every
 // thread: 16 lanes per row as in mv_rows (coalesced, four loads in flight).
 template <typename T, int NT>

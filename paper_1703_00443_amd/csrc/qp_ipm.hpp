@@ -20,10 +20,13 @@
 //   static constexpr bool kRefineAlways        refine every combined direction
 //   static constexpr bool kSolveGz             solve_g(f, r4, dz, dnu, gz) also
 //                                              returns G dz (see solve_gz)
-//   static constexpr bool kFormResidual        factor_res(D, z, lam, gz, gtl)
-//                                              factors as factor(D) and returns
-//                                              G z and G^T lam from the rows of G
-//                                              the formation of H reads
+//   static constexpr bool kFormResidual        factor_res(D, z, lam, s, h, gz,
+//                                              gtl, gtw, wsc) factors as factor(D)
+//                                              and returns G z, G^T lam and the
+//                                              affine step's G^T (lam + D r_s)
+//                                              from the rows of G the formation
+//                                              of H reads (wsc: m entries of
+//                                              scratch)
 //   bool finish(D)                             write the factor of [H A^T; A 0]
 //                                              at D to the state (false: none)
 #pragma once
@@ -228,13 +231,15 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
     for (it = 0;; ++it) {
         // residuals: rx = -(Qs z + q + G^T lam + A^T nu), rz = -(G z + s - h), ry = -(A z - b).
         // Where G is streamed (F::kFormResidual), H is formed and factored
-        // first, at D = lam / s, and G z and G^T lam come from the same reads
-        // of G; the stop test and the status logic below are unchanged.
+        // first, at D = lam / s, and G z, G^T lam and the affine right-hand
+        // side's G^T (lam + D rz) (into f; rz serves as scratch until it is
+        // set below) come from the same reads of G; the stop test and the
+        // status logic below are unchanged.
         bool ok_res = true;
         if constexpr (F::kFormResidual) {
             for (int k = tid; k < m; k += NT) D[k] = lam[k] / s[k];
             __syncthreads();
-            ok_res = fac.factor_res(D, z, lam, tm, rx);
+            ok_res = fac.factor_res(D, z, lam, s, Ph, tm, rx, f, rz);
         } else {
             fac.g_mv(z, tm);
             fac.gt_mv(lam, rx);
@@ -301,9 +306,11 @@ __device__ __forceinline__ void ipm_solve(const Prob<T> &P, T *sm, const IpmLayo
         for (int k = tid; k < p; k += NT) nup[k] = nu[k];
 
         // ---- affine direction: f = rx + G^T (lam + D rz), r4 = ry
-        for (int k = tid; k < m; k += NT) tm[k] = lam[k] + D[k] * rz[k];
-        __syncthreads();
-        fac.gt_mv(tm, f);
+        if constexpr (!F::kFormResidual) {
+            for (int k = tid; k < m; k += NT) tm[k] = lam[k] + D[k] * rz[k];
+            __syncthreads();
+            fac.gt_mv(tm, f);
+        }
         for (int i = tid; i < n; i += NT) f[i] += rx[i];
         __syncthreads();
         solve_gz<T>(fac, f, ry, dza, dna, tm);

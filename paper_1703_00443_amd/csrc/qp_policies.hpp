@@ -458,14 +458,19 @@ struct TiledFactor {
     // k loop runs outside the tile loop so that the MFMAs of the tiles of a
     // wavefront are independent and overlap their operand loads.
     // RES (G streamed in chunks): each staged chunk of rows also gives its
-    // entries of gz = G zr (16 lanes per row, as mv_rows) and its terms of
-    // gtl = G^T lr (one thread per column, n <= NT), so that the residual of
-    // the iterate needs no pass of its own over G.
+    // entries of gz = G zr (16 lanes per row, as mv_rows), the row weights
+    // wsc = lr + D rz with rz = -(gz + sv - hv), and its terms of gtl = G^T lr
+    // and gtw = G^T wsc (one thread per column, n <= NT), so that neither the
+    // residual of the iterate nor the affine right-hand side needs a pass of
+    // its own over G.
     template <bool RES = false>
     __device__ __forceinline__ void form(const T *D, const T *zr = nullptr, const T *lr = nullptr,
-                                         T *gz = nullptr, T *gtl = nullptr) {
+                                         const T *sv = nullptr, const T *hv = nullptr,
+                                         T *gz = nullptr, T *gtl = nullptr, T *gtw = nullptr,
+                                         T *wsc = nullptr) {
         static_assert(!RES || (!GL && 16 * NTL <= NT), "column sums take one thread per column");
         T cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;  // column threadIdx.x of G^T lr, rows k mod 4
+        T cw0 = 0, cw1 = 0, cw2 = 0, cw3 = 0;  // column threadIdx.x of G^T wsc
         if (UNIT && unit) ur.diag(D, xv, n);  // G^T D G is diagonal
         lane_ids();
 #pragma unroll
@@ -499,20 +504,7 @@ struct TiledFactor {
                 __syncthreads();
                 lane_ids();
             }
-            if constexpr (RES) {
-                mv_rows<T, NT>(G, ldg, rows, n, zr, gz + k0);
-                const int i = threadIdx.x;
-                if (i < n) {
-                    int k = 0;
-                    for (; k + 3 < rows; k += 4) {
-                        cs0 += G[(size_t)k * ldg + i] * lr[k0 + k];
-                        cs1 += G[(size_t)(k + 1) * ldg + i] * lr[k0 + k + 1];
-                        cs2 += G[(size_t)(k + 2) * ldg + i] * lr[k0 + k + 2];
-                        cs3 += G[(size_t)(k + 3) * ldg + i] * lr[k0 + k + 3];
-                    }
-                    for (; k < rows; ++k) cs0 += G[(size_t)k * ldg + i] * lr[k0 + k];
-                }
-            }
+            if constexpr (RES) chunk_rows_res<T, NT>(G, ldg, k0, rows, n, zr, lr, D, sv, hv, gz, wsc);
             for (int kb = 0; kb < rows; kb += 4) {
                 const int k = kb + g;
                 const T *Gk = G + (size_t)k * ldg;
@@ -525,6 +517,30 @@ struct TiledFactor {
                     sq[s] = Mfma<T>::mma(Gk[16 * I + c], dk * Gk[16 * J + c], sq[s]);
                 }
             }
+            if constexpr (RES) {
+                __syncthreads();  // the chunk's row weights
+                const int i = threadIdx.x;
+                if (i < n) {
+                    int k = 0;
+                    for (; k + 3 < rows; k += 4) {
+                        const T g0 = G[(size_t)k * ldg + i], g1 = G[(size_t)(k + 1) * ldg + i];
+                        const T g2 = G[(size_t)(k + 2) * ldg + i], g3 = G[(size_t)(k + 3) * ldg + i];
+                        cs0 += g0 * lr[k0 + k];
+                        cs1 += g1 * lr[k0 + k + 1];
+                        cs2 += g2 * lr[k0 + k + 2];
+                        cs3 += g3 * lr[k0 + k + 3];
+                        cw0 += g0 * wsc[k0 + k];
+                        cw1 += g1 * wsc[k0 + k + 1];
+                        cw2 += g2 * wsc[k0 + k + 2];
+                        cw3 += g3 * wsc[k0 + k + 3];
+                    }
+                    for (; k < rows; ++k) {
+                        const T g0 = G[(size_t)k * ldg + i];
+                        cs0 += g0 * lr[k0 + k];
+                        cw0 += g0 * wsc[k0 + k];
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -534,7 +550,10 @@ struct TiledFactor {
                 if (Mfma<T>::row(g, r) < c) sq[s][r] = T(0);  // X part of the diagonal tile
         }
         if constexpr (RES)
-            if ((int)threadIdx.x < n) gtl[threadIdx.x] = (cs0 + cs1) + (cs2 + cs3);
+            if ((int)threadIdx.x < n) {
+                gtl[threadIdx.x] = (cs0 + cs1) + (cs2 + cs3);
+                gtw[threadIdx.x] = (cw0 + cw1) + (cw2 + cw3);
+            }
     }
 
     // The register tiles from a symmetric n x n matrix whose strict lower
@@ -751,12 +770,13 @@ struct TiledFactor {
         return true;
     }
 
-    // factor(D), plus gz = G zr and gtl = G^T lr from the chunks of G that the
-    // formation stages (visible to every thread when it returns: chol_inv
-    // starts with a barrier)
-    __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, T *gz, T *gtl) {
+    // factor(D), plus gz = G zr, gtl = G^T lr and gtw = G^T (lr + D rz),
+    // rz = -(gz + sv - hv), from the chunks of G that the formation stages
+    // (visible to every thread when it returns: chol_inv starts with a barrier)
+    __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, const T *sv,
+                                               const T *hv, T *gz, T *gtl, T *gtw, T *wsc) {
         static_assert(kFormResidual, "dense-G instantiations only");
-        form<true>(D, zr, lr, gz, gtl);
+        form<true>(D, zr, lr, sv, hv, gz, gtl, gtw, wsc);
         if (!chol_inv()) return false;
         if constexpr (EQ) return schur();
         return true;

@@ -128,15 +128,19 @@ struct StreamFactor {
     }
 
     // RES: the first pass over the tiles also takes gz = G zr (16 lanes per
-    // row, as mv_rows) and gtl = G^T lr (accumulated in gtl by the thread that
-    // owns the column) from each staged chunk, so that the residual of the
-    // iterate needs no pass of its own over G.
+    // row, as mv_rows), the row weights wsc = lr + D rz with
+    // rz = -(gz + sv - hv), gtl = G^T lr and gtw = G^T wsc (accumulated by the
+    // thread that owns the column) from each staged chunk, so that neither the
+    // residual of the iterate nor the affine right-hand side needs a pass of
+    // its own over G.
     template <bool RES = false>
     __device__ __forceinline__ void form(const T *D, const T *zr = nullptr, const T *lr = nullptr,
-                                         T *gz = nullptr, T *gtl = nullptr) {
+                                         const T *sv = nullptr, const T *hv = nullptr,
+                                         T *gz = nullptr, T *gtl = nullptr, T *gtw = nullptr,
+                                         T *wsc = nullptr) {
         if (UNIT && unit) ur.diag(D, xv, n);  // G^T D G is diagonal
         if constexpr (RES)
-            for (int i = threadIdx.x; i < n; i += NT) gtl[i] = T(0);
+            for (int i = threadIdx.x; i < n; i += NT) { gtl[i] = T(0); gtw[i] = T(0); }
         lane_ids();
         // upper tiles start at zero (they become X^T = L^{-T} strictly above the diagonal)
         for (int t = w; t < nt * nt; t += kTiledWaves) {
@@ -209,23 +213,8 @@ struct StreamFactor {
                 }
                 __syncthreads();
                 lane_ids();
-                if constexpr (RES) {
-                    if (t0 == 0) {
-                        mv_rows<T, NT>(gbuf, ldg, rows, n, zr, gz + k0);
-                        for (int i = threadIdx.x; i < n; i += NT) {
-                            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-                            int k = 0;
-                            for (; k + 3 < rows; k += 4) {
-                                a0 += gbuf[k * ldg + i] * lr[k0 + k];
-                                a1 += gbuf[(k + 1) * ldg + i] * lr[k0 + k + 1];
-                                a2 += gbuf[(k + 2) * ldg + i] * lr[k0 + k + 2];
-                                a3 += gbuf[(k + 3) * ldg + i] * lr[k0 + k + 3];
-                            }
-                            for (; k < rows; ++k) a0 += gbuf[k * ldg + i] * lr[k0 + k];
-                            gtl[i] += (a0 + a1) + (a2 + a3);
-                        }
-                    }
-                }
+                if constexpr (RES)
+                    if (t0 == 0) chunk_rows_res<T, NT>(gbuf, ldg, k0, rows, n, zr, lr, D, sv, hv, gz, wsc);
                 for (int kb = 0; kb < rows; kb += 4) {
                     const int k = kb + g;
                     const T *Gk = gbuf + k * ldg;
@@ -243,6 +232,34 @@ struct StreamFactor {
                     for (int j = 0; j < GT; ++j) {
                         if (ti[j] < 0) continue;
                         acc[j] = Mfma<T>::mma(av[j], bv[j], acc[j]);
+                    }
+                }
+                if constexpr (RES) {
+                    if (t0 == 0) {
+                        __syncthreads();  // the chunk's row weights
+                        for (int i = threadIdx.x; i < n; i += NT) {
+                            T a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+                            int k = 0;
+                            for (; k + 3 < rows; k += 4) {
+                                const T g0 = gbuf[k * ldg + i], g1 = gbuf[(k + 1) * ldg + i];
+                                const T g2 = gbuf[(k + 2) * ldg + i], g3 = gbuf[(k + 3) * ldg + i];
+                                a0 += g0 * lr[k0 + k];
+                                a1 += g1 * lr[k0 + k + 1];
+                                a2 += g2 * lr[k0 + k + 2];
+                                a3 += g3 * lr[k0 + k + 3];
+                                b0 += g0 * wsc[k0 + k];
+                                b1 += g1 * wsc[k0 + k + 1];
+                                b2 += g2 * wsc[k0 + k + 2];
+                                b3 += g3 * wsc[k0 + k + 3];
+                            }
+                            for (; k < rows; ++k) {
+                                const T g0 = gbuf[k * ldg + i];
+                                a0 += g0 * lr[k0 + k];
+                                b0 += g0 * wsc[k0 + k];
+                            }
+                            gtl[i] += (a0 + a1) + (a2 + a3);
+                            gtw[i] += (b0 + b1) + (b2 + b3);
+                        }
                     }
                 }
             }
@@ -409,11 +426,13 @@ struct StreamFactor {
         return true;
     }
 
-    // factor(D), plus gz = G zr and gtl = G^T lr from the chunks of G that the
-    // formation stages (form() ends with a barrier)
-    __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, T *gz, T *gtl) {
+    // factor(D), plus gz = G zr, gtl = G^T lr and gtw = G^T (lr + D rz),
+    // rz = -(gz + sv - hv), from the chunks of G that the formation stages
+    // (form() ends with a barrier)
+    __device__ __forceinline__ bool factor_res(const T *D, const T *zr, const T *lr, const T *sv,
+                                               const T *hv, T *gz, T *gtl, T *gtw, T *wsc) {
         static_assert(kFormResidual, "dense-G instantiations only");
-        form<true>(D, zr, lr, gz, gtl);
+        form<true>(D, zr, lr, sv, hv, gz, gtl, gtw, wsc);
         if (!chol_inv()) return false;
         if constexpr (EQ) return schur();
         return true;
